@@ -1,0 +1,239 @@
+/*
+ * igg.h -- C ABI of the MI355X explicit 3-D diffusion library with implicit
+ * global grid halo updates.
+ *
+ * Paper: S. Omlin, L. Raess, I. Utkin, "Distributed Parallelization of xPU
+ * Stencil Computations in Julia", JuliaCon proceedings (arXiv 2211.15716).
+ * The API follows the paper's three-function model (Sec. 2: create the
+ * implicit global grid, update halos, finalize it), the global-size queries
+ * used by the Fig. 1 listing, and the listing's `step!` kernel fused with the
+ * halo update under boundary-first overlap (Fig. 1, `@hide_communication`).
+ * Beside the paper it offers an adjoint of the step, FP32 and FP16-storage
+ * forms and the staggered flux form of the same update.
+ *
+ * General rules
+ *   - Every function returns an int status: IGG_OK (0) or a negative
+ *     IGG_ERR_* code; igg_last_error() returns a message for the calling
+ *     thread's last failure.
+ *   - Fields are dense device arrays in HBM, x fastest: element (i,j,k) is
+ *     at data[i + nx*(j + ny*k)] (a torch tensor of shape (nz,ny,nx)).
+ *     The caller owns every field.  Indices 0 and n-1 of each dimension are
+ *     halo planes; 1..n-2 are the inner points.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls are
+ *     asynchronous and ordered with respect to it, except igg_reduce and
+ *     diffusion_dt, which synchronise it to return a host value.
+ *   - Argument checks all run on the host before any HIP call, so a call
+ *     with invalid arguments fails without touching the GPU.
+ *   - One grid exists per process (the paper's calls take no handle).  The
+ *     library owns its halo buffers, one helper stream and its events; they
+ *     are created on the current HIP device at the first call that needs the
+ *     GPU, and released by igg_finalize_global_grid.  Calls that overlap in
+ *     time (from several host threads, or on unordered streams) race on the
+ *     shared halo buffers and are not supported.
+ */
+#ifndef IGG_MI355X_H
+#define IGG_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ codes */
+#define IGG_OK 0
+#define IGG_ERR_STATE (-1) /* grid not initialised, or initialised twice      */
+#define IGG_ERR_ARG (-2)   /* null pointer or out-of-range scalar argument    */
+#define IGG_ERR_SIZE (-3)  /* field sizes do not fit the grid or each other   */
+#define IGG_ERR_DTYPE (-4) /* unsupported or mixed element types              */
+#define IGG_ERR_ALIAS (-5) /* an output field shares memory with an input     */
+#define IGG_ERR_HIP (-6)   /* a HIP runtime call failed (message has details) */
+
+/* element types */
+#define IGG_F64 0 /* double: FP64 storage and arithmetic                      */
+#define IGG_F32 1 /* float: FP32 storage and arithmetic                       */
+#define IGG_F16 2 /* _Float16 storage, FP32 arithmetic                        */
+
+/* rounding of FP16 stores */
+#define IGG_ROUND_NEAREST 0    /* round to nearest even                        */
+#define IGG_ROUND_STOCHASTIC 1 /* unbiased stochastic rounding (see below)     */
+
+/* reductions (igg_reduce) */
+#define IGG_RED_MAX 0          /* max over ALL points of a (maximum(Ci))       */
+#define IGG_RED_MIN 1          /* min over ALL points of a                      */
+#define IGG_RED_SUM 2          /* sum of a over inner points                    */
+#define IGG_RED_SUM_RATIO 3    /* sum of a/b over inner points                  */
+#define IGG_RED_HALF_SQDIFF 4  /* 0.5*sum (a-b)^2 over inner points (the loss)  */
+#define IGG_RED_DOT 5          /* sum a*b over inner points                     */
+#define IGG_RED_MAX_ABS_DIFF 6 /* max |a-b| over inner points                   */
+#define IGG_RED_MAX_ABS 7      /* max |a| over inner points                     */
+
+#define IGG_MAX_FIELDS 8 /* fields per igg_update_halo call */
+
+/* A field: a device pointer, its element type and its size per dimension. */
+typedef struct igg_field {
+    void *data;       /* device pointer, 16-byte alignment gives vector loads */
+    int32_t dtype;    /* IGG_F64, IGG_F32 or IGG_F16                          */
+    int32_t reserved; /* must be 0                                            */
+    int64_t size[3];  /* nx, ny, nz of this field                             */
+} igg_field;
+
+/* Rounding of FP16 stores.  Stochastic rounding draws its random bits from a
+ * counter-based hash of (seed, counter, point index), so the same step with
+ * the same counter rounds identically however the work is split; exactly
+ * representable values are never moved.  Pass a new counter every step. */
+typedef struct igg_rounding {
+    int32_t mode;     /* IGG_ROUND_NEAREST or IGG_ROUND_STOCHASTIC */
+    int32_t reserved; /* must be 0 */
+    uint64_t seed;
+    uint64_t counter;
+} igg_rounding;
+
+/* ------------------------------------------------------- grid (Sec. 2) */
+
+/* Create the implicit global grid (Sec. 2; Fig. 1 `init_global_grid`).
+ *   nx, ny, nz   local grid size; each must exceed the overlap (n >= ol+1).
+ *   dims         processes per dimension, NULL or 0 = automatic; this library
+ *                runs one process, so the product must be 1.
+ *   periods      1 = periodic dimension, 0 = not; NULL = (0,0,0).
+ *   overlaps     planes shared by neighbouring local grids, >= 2; NULL=(2,2,2).
+ *   me           out, nullable: this process's rank (always 0).
+ * Pure host work: no HIP call is made.
+ * Errors: IGG_ERR_STATE if a grid exists, IGG_ERR_ARG for a bad value. */
+int igg_init_global_grid(int nx, int ny, int nz, const int dims[3], const int periods[3],
+                         const int overlaps[3], int *me);
+
+/* Global grid size per dimension (Fig. 1 `nx_g()`, `ny_g()`, `nz_g()`):
+ * n_g = dims*(n-ol) + ol*(1-period).  Errors: IGG_ERR_STATE, IGG_ERR_ARG. */
+int igg_global_size(int64_t n_g[3]);
+
+/* Grid description: any pointer may be NULL.  coords is the process's
+ * Cartesian position (0,0,0).  Errors: IGG_ERR_STATE. */
+int igg_topology(int n[3], int dims[3], int periods[3], int overlaps[3], int coords[3]);
+
+/* Halo update of up to IGG_MAX_FIELDS fields (Fig. 1 `update_halo!`, Sec. 2).
+ * For each dimension in the order x, y, z, and each periodic one: pack the
+ * planes ol_A-1 and n_A-ol_A of every field into send buffers, exchange them
+ * with the neighbours (here the process itself: the upper neighbour receives
+ * plane ol_A-1, the lower one plane n_A-ol_A), and unpack them into planes
+ * n_A-1 and 0.  Full planes move, so edges and corners come out right.
+ * A field may have the grid size n or n+1 per dimension (staggered faces);
+ * its overlap is then ol_A = ol + (n_A - n).  Non-periodic dimensions are
+ * left as they are.  Fields may have different element types.
+ * Errors: IGG_ERR_STATE, IGG_ERR_ARG (null, nfields outside 1..IGG_MAX_FIELDS,
+ * reserved != 0), IGG_ERR_SIZE, IGG_ERR_DTYPE, IGG_ERR_ALIAS (two fields with
+ * the same data pointer), IGG_ERR_HIP. */
+int igg_update_halo(const igg_field *fields, int nfields, void *stream);
+
+/* Finalize the grid (Fig. 1 `finalize_global_grid`): wait for the library's
+ * stream, free buffers, stream and events, forget the grid.
+ * Errors: IGG_ERR_STATE if no grid exists, IGG_ERR_HIP. */
+int igg_finalize_global_grid(void);
+
+/* ---------------------------------------------------------- step (Fig. 1) */
+
+/* One explicit diffusion step fused with the halo update of T2, i.e. the
+ * body of Fig. 1's time loop:
+ *   T2 = T + dt*(lam*Ci*(d2x(T)/dx^2 + d2y(T)/dy^2 + d2z(T)/dz^2))
+ * on the inner points, d2x(T) = (T[i+1]-T[i]) - (T[i]-T[i-1]), followed by
+ * igg_update_halo(T2).  T, T2 and Ci must have the grid size n and one
+ * element type; T must carry a valid halo (the previous step's update).
+ *   split  boundary widths (Fig. 1 `@hide_communication (16, 2, 2)`), counted
+ *          from the array edge including the halo plane, each >= overlap.
+ *          The boundary slabs are computed first on the library's helper
+ *          stream, then the halo of T2 is updated there, while the inner
+ *          region runs on `stream`; `stream` then waits for the helper.
+ *          NULL = no overlap: everything runs on `stream` in order.
+ *   rnd    FP16 store rounding, NULL = round to nearest even (ignored for
+ *          FP64/FP32).
+ * Arithmetic: FP64 for IGG_F64; FP32 for IGG_F32 and IGG_F16 with dt*lam and
+ * 1/dd^2 rounded once from FP64.  The result does not depend on `split`.
+ * Errors: IGG_ERR_STATE, IGG_ERR_ARG, IGG_ERR_SIZE, IGG_ERR_DTYPE,
+ * IGG_ERR_ALIAS (T2 overlapping T or Ci), IGG_ERR_HIP. */
+int diffusion_step(const igg_field *T2, const igg_field *T, const igg_field *Ci, double lam,
+                   double dt, double dx, double dy, double dz, const int split[3],
+                   const igg_rounding *rnd, void *stream);
+
+/* Stable time step of Fig. 1: dt = min(dx^2,dy^2,dz^2)/lam/maximum(Ci)/6.1,
+ * the maximum taken in FP64 over every point of Ci on the GPU.
+ * Synchronises `stream`.  Errors: as igg_reduce, IGG_ERR_ARG for lam <= 0. */
+int diffusion_dt(const igg_field *Ci, double lam, double dx, double dy, double dz, double *dt,
+                 void *stream);
+
+/* Adjoint of diffusion_step.  With a = dt*lam and L the operator
+ * sum_d d2_d(.)/dd^2, the step is T_{n+1} = T_n + a*Ci.*(L T_n); given the
+ * incoming adjoint lam_np1 = dLoss/dT_{n+1} (with a valid halo) it computes
+ *   lam_n = lam_np1 + a*L(Ci.*lam_np1)     (inner points), then halo(lam_n)
+ *   gCi  += a*lam_np1.*(L T_n)             (inner points; halo untouched)
+ * T_n is the state the forward step read (valid halo); Ci needs a valid halo.
+ * FP64 or FP32 (IGG_ERR_DTYPE for FP16).  `split` as in diffusion_step.
+ * Errors: as diffusion_step; IGG_ERR_ALIAS if lam_n or gCi overlaps an input
+ * or each other. */
+int diffusion_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1,
+                           const igg_field *T_n, const igg_field *Ci, const igg_field *gCi,
+                           double lam, double dt, double dx, double dy, double dz,
+                           const int split[3], void *stream);
+
+/* ---------------------------------------------- staggered flux form */
+
+/* Flux form of the same step on the staggered grid (Sec. 2 "regular
+ * staggered grid"): face fluxes qx (nx+1,ny,nz), qy (nx,ny+1,nz),
+ * qz (nx,ny,nz+1) with face f between cells f-1 and f,
+ *   qx[f] = -lam*(T[f]-T[f-1])/dx       faces 1..nx-1 of the inner rows
+ *   T2    = T - dt*Ci*((qx[i+1]-qx[i])/dx + (qy[j+1]-qy[j])/dy + (qz[k+1]-qz[k])/dz)
+ * then one halo update of {T2, qx, qy, qz}.  FP64 or FP32.  split: NULL (no
+ * overlap) only in this version.  Errors: as diffusion_step. */
+int diffusion_flux_step(const igg_field *T2, const igg_field *T, const igg_field *Ci,
+                        const igg_field *qx, const igg_field *qy, const igg_field *qz, double lam,
+                        double dt, double dx, double dy, double dz, void *stream);
+
+/* Adjoint of diffusion_flux_step: with mu = Ci.*lam_np1 and the adjoint face
+ * fluxes p = -lam*grad(mu) (written into px, py, pz, face-field sized work
+ * arrays), lam_n = lam_np1 - dt*div(p) on inner cells, then halo(lam_n), and
+ * gCi += -dt*lam_np1.*div(q_n) with q_n = (qx,qy,qz) the forward fluxes of
+ * step n.  Errors: as diffusion_step_adjoint. */
+int diffusion_flux_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1,
+                                const igg_field *Ci, const igg_field *qx, const igg_field *qy,
+                                const igg_field *qz, const igg_field *px, const igg_field *py,
+                                const igg_field *pz, const igg_field *gCi, double lam, double dt,
+                                double dx, double dy, double dz, void *stream);
+
+/* --------------------------------------------------------- reductions */
+
+/* FP64 reduction of one or two fields (IGG_RED_*); b is needed by
+ * SUM_RATIO, HALF_SQDIFF, DOT and MAX_ABS_DIFF and ignored otherwise.  Any
+ * element type; values are widened to FP64 before they are combined, in a
+ * fixed order, so repeated calls give identical bits.  The result is written
+ * to *out (host memory) after `stream` is synchronised.
+ * Errors: IGG_ERR_STATE, IGG_ERR_ARG, IGG_ERR_SIZE (a, b differ),
+ * IGG_ERR_DTYPE, IGG_ERR_HIP. */
+int igg_reduce(int op, const igg_field *a, const igg_field *b, double *out, void *stream);
+
+/* --------------------------------------------------------- host helpers */
+
+/* The boundary-first partition used by diffusion_step for grid size n and
+ * widths split: up to 6 disjoint boundary boxes followed by the inner box,
+ * each as {i0,i1,j0,j1,k0,k1} (half-open).  Empty boxes are dropped; the
+ * inner box is last and may be empty (i0 == i1).  *nboxes counts all boxes
+ * written.  Pure host function.  Errors: IGG_ERR_ARG. */
+int igg_plan_split(const int n[3], const int split[3], int boxes[7][6], int *nboxes);
+
+/* Kernel timing of the dominant kernel.  While enabled, each launch of the
+ * inner-region step kernel is bracketed by two HIP events on the stream it
+ * runs on; igg_timing_read synchronises those events and returns the summed
+ * duration in milliseconds, the launch count and the number of inner points
+ * those launches computed, then resets the totals.  Errors: IGG_ERR_HIP. */
+int igg_timing_enable(int on);
+int igg_timing_read(double *ms, int64_t *launches, int64_t *points);
+
+/* Message for the calling thread's last failure ("" if none). */
+const char *igg_last_error(void);
+
+/* Library version string. */
+const char *igg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IGG_MI355X_H */

@@ -1,0 +1,603 @@
+// api.hip -- the extern "C" entry points of igg.h: argument checks (all on
+// the host, before any HIP call), the implicit global grid state and the
+// boundary-first schedule of the step.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "host.hpp"
+
+namespace igg {
+
+static thread_local std::string t_last_error;
+
+int fail(int code, const std::string &msg)
+{
+    t_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    char buf[512];
+    snprintf(buf, sizeof buf, "HIP error %d (%s) in %s", (int)e, hipGetErrorString(e), what);
+    return fail(IGG_ERR_HIP, buf);
+}
+
+Grid &grid()
+{
+    static Grid g;
+    return g;
+}
+
+int elem_bytes(int dtype) { return dtype == IGG_F64 ? 8 : dtype == IGG_F32 ? 4 : 2; }
+
+int64_t field_elems(const igg_field &f) { return f.size[0] * f.size[1] * f.size[2]; }
+
+bool overlaps_mem(const igg_field &a, const igg_field &b)
+{
+    uintptr_t a0 = (uintptr_t)a.data, a1 = a0 + (uintptr_t)(field_elems(a) * elem_bytes(a.dtype));
+    uintptr_t b0 = (uintptr_t)b.data, b1 = b0 + (uintptr_t)(field_elems(b) * elem_bytes(b.dtype));
+    return a0 < b1 && b0 < a1;
+}
+
+int check_field(const igg_field *f, const char *name, bool grid_sized)
+{
+    Grid &g = grid();
+    if (!f) return fail(IGG_ERR_ARG, std::string(name) + ": null field");
+    if (!f->data) return fail(IGG_ERR_ARG, std::string(name) + ": null data pointer");
+    if (f->reserved != 0) return fail(IGG_ERR_ARG, std::string(name) + ": reserved must be 0");
+    if (f->dtype < IGG_F64 || f->dtype > IGG_F16)
+        return fail(IGG_ERR_DTYPE, std::string(name) + ": unknown dtype " + std::to_string(f->dtype));
+    for (int d = 0; d < 3; ++d) {
+        int64_t s = f->size[d];
+        bool ok = grid_sized ? (s == g.n[d]) : (s == g.n[d] || s == g.n[d] + 1);
+        if (!ok) {
+            char buf[256];
+            snprintf(buf, sizeof buf, "%s: size (%lld,%lld,%lld) does not fit the grid (%d,%d,%d)%s",
+                     name, (long long)f->size[0], (long long)f->size[1], (long long)f->size[2],
+                     g.n[0], g.n[1], g.n[2], grid_sized ? "" : " (n or n+1 per dimension)");
+            return fail(IGG_ERR_SIZE, buf);
+        }
+    }
+    return IGG_OK;
+}
+
+static int check_finite_pos(double v, const char *name, bool allow_zero)
+{
+    if (!isfinite(v) || v < 0.0 || (!allow_zero && v == 0.0))
+        return fail(IGG_ERR_ARG, std::string(name) + " must be finite and " +
+                                     (allow_zero ? "non-negative" : "positive"));
+    return IGG_OK;
+}
+
+int plan_split(const int n[3], const int w[3], Split &s)
+{
+    s.nb = 0;
+    int kz0 = std::min(w[2], n[2] - 1), kz1 = std::max(n[2] - w[2], kz0);
+    int jy0 = std::min(w[1], n[1] - 1), jy1 = std::max(n[1] - w[1], jy0);
+    int ix0 = std::min(w[0], n[0] - 1), ix1 = std::max(n[0] - w[0], ix0);
+    auto add = [&](int i0, int i1, int j0, int j1, int k0, int k1) {
+        if (i0 < i1 && j0 < j1 && k0 < k1) s.boundary[s.nb++] = Box{i0, i1, j0, j1, k0, k1};
+    };
+    const int X = n[0] - 1, Y = n[1] - 1, Z = n[2] - 1;
+    add(1, X, 1, Y, 1, kz0);        // z low slab
+    add(1, X, 1, Y, kz1, Z);        // z high slab
+    add(1, X, 1, jy0, kz0, kz1);    // y low slab
+    add(1, X, jy1, Y, kz0, kz1);    // y high slab
+    add(1, ix0, jy0, jy1, kz0, kz1);  // x low slab
+    add(ix1, X, jy0, jy1, kz0, kz1);  // x high slab
+    s.inner = Box{ix0, ix1, jy0, jy1, kz0, kz1};
+    return IGG_OK;
+}
+
+BoxSet make_boxset(const Box *b, int nb)
+{
+    BoxSet bs{};
+    bs.n = nb;
+    int64_t t = 0;
+    for (int q = 0; q < nb; ++q) {
+        int w = b[q].i1 - b[q].i0;
+        int lg = 3;
+        while ((1 << lg) < w && lg < 6) ++lg;
+        bs.b[q] = b[q];
+        bs.lpr_log2[q] = lg;
+        bs.nseg_x[q] = (w + (1 << lg) - 1) >> lg;
+        bs.first[q] = t;
+        t += (int64_t)bs.nseg_x[q] * (b[q].j1 - b[q].j0) * (b[q].k1 - b[q].k0) << lg;
+    }
+    for (int q = nb; q < 7; ++q) bs.first[q] = t;
+    return bs;
+}
+
+uint32_t sr_key(uint64_t seed, uint64_t counter)
+{
+    uint32_t h = pcg_hash((uint32_t)(counter >> 32));
+    h = pcg_hash((uint32_t)counter ^ h);
+    h = pcg_hash((uint32_t)(seed >> 32) ^ h);
+    return pcg_hash((uint32_t)seed ^ h);
+}
+
+int ensure_device()
+{
+    Grid &g = grid();
+    int dev = -1;
+    IGG_HIP(hipGetDevice(&dev));
+    if (g.dev_ready) {
+        if (dev != g.device)
+            return fail(IGG_ERR_ARG, "the grid's GPU resources live on device " + std::to_string(g.device) +
+                                         ", current device is " + std::to_string(dev));
+        return IGG_OK;
+    }
+    // default priority: the helper stream is an ordinary second stream
+    IGG_HIP(hipStreamCreateWithFlags(&g.side, hipStreamNonBlocking));
+    IGG_HIP(hipEventCreateWithFlags(&g.ev_fork, hipEventDisableTiming));
+    IGG_HIP(hipEventCreateWithFlags(&g.ev_join, hipEventDisableTiming));
+    // one plane of the largest field (n+1 per dimension) in FP64, rounded to 256 B
+    int64_t m0 = (int64_t)(g.n[1] + 1) * (g.n[2] + 1), m1 = (int64_t)(g.n[0] + 1) * (g.n[2] + 1),
+            m2 = (int64_t)(g.n[0] + 1) * (g.n[1] + 1);
+    int64_t cap = std::max(m0, std::max(m1, m2)) * 8;
+    g.halo_cap = (size_t)((cap + 255) / 256 * 256);
+    IGG_HIP(hipMalloc((void **)&g.halo_buf, g.halo_cap * 2 * 2 * IGG_MAX_FIELDS));
+    IGG_HIP(hipMalloc((void **)&g.red_part, 8192 * sizeof(double)));
+    IGG_HIP(hipHostMalloc((void **)&g.red_host, 64 * sizeof(double), hipHostMallocDefault));
+    g.device = dev;
+    g.dev_ready = true;
+    return IGG_OK;
+}
+
+static int release_device()
+{
+    Grid &g = grid();
+    if (!g.dev_ready) return IGG_OK;
+    int rc = IGG_OK;
+    auto chk = [&](hipError_t e, const char *w) {
+        if (e != hipSuccess && rc == IGG_OK) rc = hip_fail(e, w);
+    };
+    chk(hipStreamSynchronize(g.side), "hipStreamSynchronize(side)");
+    chk(hipFree(g.halo_buf), "hipFree(halo_buf)");
+    chk(hipFree(g.red_part), "hipFree(red_part)");
+    chk(hipHostFree(g.red_host), "hipHostFree(red_host)");
+    chk(hipEventDestroy(g.ev_fork), "hipEventDestroy");
+    chk(hipEventDestroy(g.ev_join), "hipEventDestroy");
+    for (hipEvent_t e : g.tev) chk(hipEventDestroy(e), "hipEventDestroy(timing)");
+    chk(hipStreamDestroy(g.side), "hipStreamDestroy(side)");
+    g.tev.clear();
+    g.dev_ready = false;
+    return rc;
+}
+
+// Bracket a launch on stream s with timing events when timing is enabled.
+static int timing_mark(hipStream_t s)
+{
+    Grid &g = grid();
+    if (!g.timing) return IGG_OK;
+    if (g.tev_used == g.tev.size()) {
+        hipEvent_t e;
+        IGG_HIP(hipEventCreate(&e));
+        g.tev.push_back(e);
+    }
+    IGG_HIP(hipEventRecord(g.tev[g.tev_used++], s));
+    return IGG_OK;
+}
+
+static int64_t box_points(const Box &b)
+{
+    return (int64_t)std::max(0, b.i1 - b.i0) * std::max(0, b.j1 - b.j0) * std::max(0, b.k1 - b.k0);
+}
+
+static int check_split(const int *split, const int *ol)
+{
+    if (!split) return IGG_OK;
+    for (int d = 0; d < 3; ++d)
+        if (split[d] < ol[d])
+            return fail(IGG_ERR_ARG, "split width " + std::to_string(split[d]) + " in dimension " +
+                                         std::to_string(d) + " is below the overlap " +
+                                         std::to_string(ol[d]));
+    return IGG_OK;
+}
+
+static int check_spacings(double lam, double dt, double dx, double dy, double dz)
+{
+    int rc;
+    if ((rc = check_finite_pos(lam, "lam", false))) return rc;
+    if ((rc = check_finite_pos(dt, "dt", true))) return rc;
+    if ((rc = check_finite_pos(dx, "dx", false))) return rc;
+    if ((rc = check_finite_pos(dy, "dy", false))) return rc;
+    if ((rc = check_finite_pos(dz, "dz", false))) return rc;
+    return IGG_OK;
+}
+
+}  // namespace igg
+
+using namespace igg;
+
+extern "C" {
+
+const char *igg_last_error(void) { return t_last_error.c_str(); }
+
+const char *igg_version(void) { return "igg-mi355x 0.1 (gfx950)"; }
+
+int igg_init_global_grid(int nx, int ny, int nz, const int dims[3], const int periods[3],
+                         const int overlaps[3], int *me)
+{
+    Grid &g = grid();
+    if (g.init) return fail(IGG_ERR_STATE, "the global grid is already initialised");
+    int n[3] = {nx, ny, nz};
+    int ol[3] = {2, 2, 2}, per[3] = {0, 0, 0}, dm[3] = {1, 1, 1};
+    for (int d = 0; d < 3; ++d) {
+        if (overlaps) ol[d] = overlaps[d];
+        if (periods) per[d] = periods[d];
+        if (dims) dm[d] = dims[d] == 0 ? 1 : dims[d];
+        if (ol[d] < 2) return fail(IGG_ERR_ARG, "overlaps must be >= 2");
+        if (per[d] != 0 && per[d] != 1) return fail(IGG_ERR_ARG, "periods must be 0 or 1");
+        if (dm[d] < 0) return fail(IGG_ERR_ARG, "dims must be >= 0");
+        if (n[d] < ol[d] + 1)
+            return fail(IGG_ERR_ARG, "local size " + std::to_string(n[d]) +
+                                         " must exceed the overlap " + std::to_string(ol[d]));
+        if (n[d] > (1 << 24)) return fail(IGG_ERR_ARG, "local size above 2^24");
+    }
+    if ((int64_t)dm[0] * dm[1] * dm[2] != 1)
+        return fail(IGG_ERR_ARG, "dims must multiply to the number of processes, which is 1");
+    if ((int64_t)(nx + 1) * (ny + 1) > 0x7fffffffLL || (int64_t)(nx + 1) * (nz + 1) > 0x7fffffffLL ||
+        (int64_t)(ny + 1) * (nz + 1) > 0x7fffffffLL)
+        return fail(IGG_ERR_ARG, "a plane of the grid exceeds 2^31 points");
+    for (int d = 0; d < 3; ++d) {
+        g.n[d] = n[d];
+        g.ol[d] = ol[d];
+        g.periods[d] = per[d];
+        g.dims[d] = dm[d];
+    }
+    g.init = true;
+    g.timing = false;
+    g.tev_used = 0;
+    g.t_ms = 0;
+    g.t_launches = g.t_points = 0;
+    if (me) *me = 0;
+    return IGG_OK;
+}
+
+int igg_global_size(int64_t n_g[3])
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    if (!n_g) return fail(IGG_ERR_ARG, "n_g is null");
+    for (int d = 0; d < 3; ++d)
+        n_g[d] = (int64_t)g.dims[d] * (g.n[d] - g.ol[d]) + (int64_t)g.ol[d] * (1 - g.periods[d]);
+    return IGG_OK;
+}
+
+int igg_topology(int n[3], int dims[3], int periods[3], int overlaps[3], int coords[3])
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    for (int d = 0; d < 3; ++d) {
+        if (n) n[d] = g.n[d];
+        if (dims) dims[d] = g.dims[d];
+        if (periods) periods[d] = g.periods[d];
+        if (overlaps) overlaps[d] = g.ol[d];
+        if (coords) coords[d] = 0;
+    }
+    return IGG_OK;
+}
+
+int igg_update_halo(const igg_field *fields, int nfields, void *stream)
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    if (!fields) return fail(IGG_ERR_ARG, "fields is null");
+    if (nfields < 1 || nfields > IGG_MAX_FIELDS)
+        return fail(IGG_ERR_ARG, "nfields must be in 1.." + std::to_string(IGG_MAX_FIELDS));
+    int rc;
+    for (int f = 0; f < nfields; ++f) {
+        std::string nm = "field " + std::to_string(f);
+        if ((rc = check_field(&fields[f], nm.c_str(), false))) return rc;
+        for (int q = 0; q < f; ++q)
+            if (overlaps_mem(fields[f], fields[q]))
+                return fail(IGG_ERR_ALIAS, "fields " + std::to_string(q) + " and " + std::to_string(f) +
+                                               " share memory");
+    }
+    if ((rc = ensure_device())) return rc;
+    return launch_halo(fields, nfields, (hipStream_t)stream);
+}
+
+int igg_finalize_global_grid(void)
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    int rc = release_device();
+    g = Grid();
+    return rc;
+}
+
+int igg_plan_split(const int n[3], const int split[3], int boxes[7][6], int *nboxes)
+{
+    if (!n || !split || !boxes || !nboxes) return fail(IGG_ERR_ARG, "null argument");
+    for (int d = 0; d < 3; ++d) {
+        if (n[d] < 3) return fail(IGG_ERR_ARG, "n must be >= 3");
+        if (split[d] < 1) return fail(IGG_ERR_ARG, "split widths must be >= 1");
+    }
+    Split s;
+    plan_split(n, split, s);
+    for (int q = 0; q < s.nb; ++q) {
+        const Box &b = s.boundary[q];
+        int v[6] = {b.i0, b.i1, b.j0, b.j1, b.k0, b.k1};
+        memcpy(boxes[q], v, sizeof v);
+    }
+    const Box &b = s.inner;
+    int v[6] = {b.i0, b.i1, b.j0, b.j1, b.k0, b.k1};
+    memcpy(boxes[s.nb], v, sizeof v);
+    *nboxes = s.nb + 1;
+    return IGG_OK;
+}
+
+int diffusion_step(const igg_field *T2, const igg_field *T, const igg_field *Ci, double lam,
+                   double dt, double dx, double dy, double dz, const int split[3],
+                   const igg_rounding *rnd, void *stream)
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    int rc;
+    if ((rc = check_field(T2, "T2", true))) return rc;
+    if ((rc = check_field(T, "T", true))) return rc;
+    if ((rc = check_field(Ci, "Ci", true))) return rc;
+    if (T2->dtype != T->dtype || Ci->dtype != T->dtype)
+        return fail(IGG_ERR_DTYPE, "T2, T and Ci must share one dtype");
+    if (overlaps_mem(*T2, *T) || overlaps_mem(*T2, *Ci))
+        return fail(IGG_ERR_ALIAS, "T2 shares memory with T or Ci");
+    if ((rc = check_spacings(lam, dt, dx, dy, dz))) return rc;
+    if ((rc = check_split(split, g.ol))) return rc;
+    int stochastic = 0;
+    uint32_t key = 0;
+    if (rnd) {
+        if (rnd->reserved != 0) return fail(IGG_ERR_ARG, "rounding.reserved must be 0");
+        if (rnd->mode != IGG_ROUND_NEAREST && rnd->mode != IGG_ROUND_STOCHASTIC)
+            return fail(IGG_ERR_ARG, "unknown rounding mode");
+        stochastic = rnd->mode == IGG_ROUND_STOCHASTIC;
+        key = sr_key(rnd->seed, rnd->counter);
+    }
+    if ((rc = ensure_device())) return rc;
+
+    hipStream_t s = (hipStream_t)stream;
+    StepArgs a{T2->data, T->data, Ci->data, g.n[0], g.n[1], g.n[2],
+               dt * lam, 1.0 / (dx * dx), 1.0 / (dy * dy), 1.0 / (dz * dz), key, stochastic};
+    if (!split) {
+        Box all{1, g.n[0] - 1, 1, g.n[1] - 1, 1, g.n[2] - 1};
+        if ((rc = timing_mark(s))) return rc;
+        if ((rc = launch_step_inner(T->dtype, a, all, s))) return rc;
+        if ((rc = timing_mark(s))) return rc;
+        if (g.timing) { g.t_launches++; g.t_points += box_points(all); }
+        return launch_halo(T2, 1, s);
+    }
+    Split sp;
+    plan_split(g.n, split, sp);
+    IGG_HIP(hipEventRecord(g.ev_fork, s));
+    IGG_HIP(hipStreamWaitEvent(g.side, g.ev_fork, 0));
+    if (sp.nb && (rc = launch_step_boxes(T->dtype, a, sp.boundary, sp.nb, g.side))) return rc;
+    if ((rc = launch_halo(T2, 1, g.side))) return rc;
+    IGG_HIP(hipEventRecord(g.ev_join, g.side));
+    if (box_points(sp.inner) > 0) {
+        if ((rc = timing_mark(s))) return rc;
+        if ((rc = launch_step_inner(T->dtype, a, sp.inner, s))) return rc;
+        if ((rc = timing_mark(s))) return rc;
+        if (g.timing) { g.t_launches++; g.t_points += box_points(sp.inner); }
+    }
+    IGG_HIP(hipStreamWaitEvent(s, g.ev_join, 0));
+    return IGG_OK;
+}
+
+int diffusion_dt(const igg_field *Ci, double lam, double dx, double dy, double dz, double *dt,
+                 void *stream)
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    int rc;
+    if ((rc = check_field(Ci, "Ci", false))) return rc;
+    if (!dt) return fail(IGG_ERR_ARG, "dt is null");
+    if ((rc = check_spacings(lam, 0.0, dx, dy, dz))) return rc;
+    if ((rc = ensure_device())) return rc;
+    double m = 0.0;
+    if ((rc = launch_reduce(IGG_RED_MAX, *Ci, nullptr, &m, (hipStream_t)stream))) return rc;
+    if (!(m > 0.0) || !isfinite(m)) return fail(IGG_ERR_ARG, "maximum(Ci) must be positive and finite");
+    double mn = std::min(dx * dx, std::min(dy * dy, dz * dz));
+    *dt = mn / lam / m / 6.1;
+    return IGG_OK;
+}
+
+int diffusion_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1,
+                           const igg_field *T_n, const igg_field *Ci, const igg_field *gCi,
+                           double lam, double dt, double dx, double dy, double dz,
+                           const int split[3], void *stream)
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    int rc;
+    if ((rc = check_field(lam_n, "lam_n", true))) return rc;
+    if ((rc = check_field(lam_np1, "lam_np1", true))) return rc;
+    if ((rc = check_field(T_n, "T_n", true))) return rc;
+    if ((rc = check_field(Ci, "Ci", true))) return rc;
+    if ((rc = check_field(gCi, "gCi", true))) return rc;
+    int dt_ = lam_n->dtype;
+    if (lam_np1->dtype != dt_ || T_n->dtype != dt_ || Ci->dtype != dt_ || gCi->dtype != dt_)
+        return fail(IGG_ERR_DTYPE, "adjoint fields must share one dtype");
+    if (dt_ == IGG_F16) return fail(IGG_ERR_DTYPE, "the adjoint runs in FP64 or FP32");
+    const igg_field *ins[3] = {lam_np1, T_n, Ci};
+    for (const igg_field *o : {lam_n, gCi})
+        for (const igg_field *i : ins)
+            if (overlaps_mem(*o, *i)) return fail(IGG_ERR_ALIAS, "an output shares memory with an input");
+    if (overlaps_mem(*lam_n, *gCi)) return fail(IGG_ERR_ALIAS, "lam_n shares memory with gCi");
+    if ((rc = check_spacings(lam, dt, dx, dy, dz))) return rc;
+    if ((rc = check_split(split, g.ol))) return rc;
+    if ((rc = ensure_device())) return rc;
+
+    hipStream_t s = (hipStream_t)stream;
+    AdjArgs a{lam_n->data, lam_np1->data, T_n->data, Ci->data, gCi->data, g.n[0], g.n[1], g.n[2],
+              dt * lam, 1.0 / (dx * dx), 1.0 / (dy * dy), 1.0 / (dz * dz)};
+    if (!split) {
+        Box all{1, g.n[0] - 1, 1, g.n[1] - 1, 1, g.n[2] - 1};
+        if ((rc = timing_mark(s))) return rc;
+        if ((rc = launch_adjoint_inner(dt_, a, all, s))) return rc;
+        if ((rc = timing_mark(s))) return rc;
+        if (g.timing) { g.t_launches++; g.t_points += box_points(all); }
+        return launch_halo(lam_n, 1, s);
+    }
+    Split sp;
+    plan_split(g.n, split, sp);
+    IGG_HIP(hipEventRecord(g.ev_fork, s));
+    IGG_HIP(hipStreamWaitEvent(g.side, g.ev_fork, 0));
+    if (sp.nb && (rc = launch_adjoint_boxes(dt_, a, sp.boundary, sp.nb, g.side))) return rc;
+    if ((rc = launch_halo(lam_n, 1, g.side))) return rc;
+    IGG_HIP(hipEventRecord(g.ev_join, g.side));
+    if (box_points(sp.inner) > 0) {
+        if ((rc = timing_mark(s))) return rc;
+        if ((rc = launch_adjoint_inner(dt_, a, sp.inner, s))) return rc;
+        if ((rc = timing_mark(s))) return rc;
+        if (g.timing) { g.t_launches++; g.t_points += box_points(sp.inner); }
+    }
+    IGG_HIP(hipStreamWaitEvent(s, g.ev_join, 0));
+    return IGG_OK;
+}
+
+static int check_face(const igg_field *q, const char *name, int dim)
+{
+    Grid &g = grid();
+    int rc;
+    if ((rc = check_field(q, name, false))) return rc;
+    for (int d = 0; d < 3; ++d)
+        if (q->size[d] != g.n[d] + (d == dim ? 1 : 0))
+            return fail(IGG_ERR_SIZE, std::string(name) + " must have n+1 points in its own dimension "
+                                                          "and n in the others");
+    return IGG_OK;
+}
+
+int diffusion_flux_step(const igg_field *T2, const igg_field *T, const igg_field *Ci,
+                        const igg_field *qx, const igg_field *qy, const igg_field *qz, double lam,
+                        double dt, double dx, double dy, double dz, void *stream)
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    int rc;
+    if ((rc = check_field(T2, "T2", true))) return rc;
+    if ((rc = check_field(T, "T", true))) return rc;
+    if ((rc = check_field(Ci, "Ci", true))) return rc;
+    if ((rc = check_face(qx, "qx", 0))) return rc;
+    if ((rc = check_face(qy, "qy", 1))) return rc;
+    if ((rc = check_face(qz, "qz", 2))) return rc;
+    int ty = T->dtype;
+    for (const igg_field *f : {T2, Ci, qx, qy, qz})
+        if (f->dtype != ty) return fail(IGG_ERR_DTYPE, "flux-form fields must share one dtype");
+    if (ty == IGG_F16) return fail(IGG_ERR_DTYPE, "the flux form runs in FP64 or FP32");
+    const igg_field *outs[4] = {T2, qx, qy, qz};
+    for (int o = 0; o < 4; ++o) {
+        if (overlaps_mem(*outs[o], *T) || overlaps_mem(*outs[o], *Ci))
+            return fail(IGG_ERR_ALIAS, "an output shares memory with T or Ci");
+        for (int p = 0; p < o; ++p)
+            if (overlaps_mem(*outs[o], *outs[p])) return fail(IGG_ERR_ALIAS, "outputs share memory");
+    }
+    if ((rc = check_spacings(lam, dt, dx, dy, dz))) return rc;
+    if ((rc = ensure_device())) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    FluxArgs a{qx->data, qy->data, qz->data, T->data, T2->data, Ci->data, g.n[0], g.n[1], g.n[2],
+               lam, dt, 1.0 / dx, 1.0 / dy, 1.0 / dz};
+    if ((rc = launch_flux(ty, a, s))) return rc;
+    if ((rc = timing_mark(s))) return rc;
+    if ((rc = launch_flux_update(ty, a, s))) return rc;
+    if ((rc = timing_mark(s))) return rc;
+    if (g.timing) { g.t_launches++; g.t_points += (int64_t)(g.n[0] - 2) * (g.n[1] - 2) * (g.n[2] - 2); }
+    igg_field hf[4] = {*T2, *qx, *qy, *qz};
+    return launch_halo(hf, 4, s);
+}
+
+int diffusion_flux_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1,
+                                const igg_field *Ci, const igg_field *qx, const igg_field *qy,
+                                const igg_field *qz, const igg_field *px, const igg_field *py,
+                                const igg_field *pz, const igg_field *gCi, double lam, double dt,
+                                double dx, double dy, double dz, void *stream)
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    int rc;
+    if ((rc = check_field(lam_n, "lam_n", true))) return rc;
+    if ((rc = check_field(lam_np1, "lam_np1", true))) return rc;
+    if ((rc = check_field(Ci, "Ci", true))) return rc;
+    if ((rc = check_field(gCi, "gCi", true))) return rc;
+    if ((rc = check_face(qx, "qx", 0))) return rc;
+    if ((rc = check_face(qy, "qy", 1))) return rc;
+    if ((rc = check_face(qz, "qz", 2))) return rc;
+    if ((rc = check_face(px, "px", 0))) return rc;
+    if ((rc = check_face(py, "py", 1))) return rc;
+    if ((rc = check_face(pz, "pz", 2))) return rc;
+    int ty = lam_n->dtype;
+    for (const igg_field *f : {lam_np1, Ci, gCi, qx, qy, qz, px, py, pz})
+        if (f->dtype != ty) return fail(IGG_ERR_DTYPE, "flux-form adjoint fields must share one dtype");
+    if (ty == IGG_F16) return fail(IGG_ERR_DTYPE, "the flux form runs in FP64 or FP32");
+    const igg_field *outs[5] = {lam_n, gCi, px, py, pz};
+    const igg_field *ins[5] = {lam_np1, Ci, qx, qy, qz};
+    for (int o = 0; o < 5; ++o) {
+        for (int i = 0; i < 5; ++i)
+            if (overlaps_mem(*outs[o], *ins[i])) return fail(IGG_ERR_ALIAS, "an output shares memory with an input");
+        for (int p = 0; p < o; ++p)
+            if (overlaps_mem(*outs[o], *outs[p])) return fail(IGG_ERR_ALIAS, "outputs share memory");
+    }
+    if ((rc = check_spacings(lam, dt, dx, dy, dz))) return rc;
+    if ((rc = ensure_device())) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    FluxAdjArgs a{lam_n->data, lam_np1->data, Ci->data, qx->data, qy->data, qz->data,
+                  px->data, py->data, pz->data, gCi->data, g.n[0], g.n[1], g.n[2],
+                  lam, dt, 1.0 / dx, 1.0 / dy, 1.0 / dz};
+    if ((rc = launch_flux_adjoint(ty, a, s))) return rc;
+    return launch_halo(lam_n, 1, s);
+}
+
+int igg_reduce(int op, const igg_field *a, const igg_field *b, double *out, void *stream)
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    if (!out) return fail(IGG_ERR_ARG, "out is null");
+    if (op < IGG_RED_MAX || op > IGG_RED_MAX_ABS) return fail(IGG_ERR_ARG, "unknown reduction");
+    int rc;
+    if ((rc = check_field(a, "a", false))) return rc;
+    bool two = op == IGG_RED_SUM_RATIO || op == IGG_RED_HALF_SQDIFF || op == IGG_RED_DOT ||
+               op == IGG_RED_MAX_ABS_DIFF;
+    if (two) {
+        if ((rc = check_field(b, "b", false))) return rc;
+        for (int d = 0; d < 3; ++d)
+            if (a->size[d] != b->size[d]) return fail(IGG_ERR_SIZE, "a and b differ in size");
+        if (a->dtype != b->dtype) return fail(IGG_ERR_DTYPE, "a and b must share one dtype");
+    }
+    if ((rc = ensure_device())) return rc;
+    return launch_reduce(op, *a, two ? b : nullptr, out, (hipStream_t)stream);
+}
+
+int igg_timing_enable(int on)
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    g.timing = on != 0;
+    return IGG_OK;
+}
+
+int igg_timing_read(double *ms, int64_t *launches, int64_t *points)
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    double total = g.t_ms;
+    for (size_t q = 0; q + 1 < g.tev_used; q += 2) {
+        float t = 0.f;
+        IGG_HIP(hipEventSynchronize(g.tev[q + 1]));
+        IGG_HIP(hipEventElapsedTime(&t, g.tev[q], g.tev[q + 1]));
+        total += t;
+    }
+    if (ms) *ms = total;
+    if (launches) *launches = g.t_launches;
+    if (points) *points = g.t_points;
+    g.tev_used = 0;
+    g.t_ms = 0;
+    g.t_launches = g.t_points = 0;
+    return IGG_OK;
+}
+
+}  // extern "C"

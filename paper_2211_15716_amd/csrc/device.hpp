@@ -1,0 +1,160 @@
+// device.hpp -- device-side building blocks shared by every kernel of the
+// library: storage/compute types, the one stencil-point function, the
+// counter-based hash and FP16 stochastic rounding, and the box descriptors
+// the boundary-first schedule hands to kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace igg {
+
+// ------------------------------------------------------------------ types
+// Storage type S and the type C the arithmetic runs in.
+template <typename S> struct Compute;
+template <> struct Compute<double> { using type = double; };
+template <> struct Compute<float> { using type = float; };
+template <> struct Compute<_Float16> { using type = float; };
+template <typename S> using compute_t = typename Compute<S>::type;
+
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+template <typename C, typename S> __device__ __forceinline__ C widen(S v) { return static_cast<C>(v); }
+
+// ------------------------------------------------------------ the stencil
+// One point of the Fig. 1 step:
+//   T2 = T + dt*lam*Ci*(d2x/dx^2 + d2y/dy^2 + d2z/dz^2),
+//   d2x = (T[i+1]-T[i]) - (T[i]-T[i-1]).
+// a = dt*lam and r* = 1/dd^2 are rounded once to C on the host.  Every
+// kernel that computes a point calls this function with the same operands
+// (the file is built with -ffp-contract=off and the fused operations are
+// explicit), so a point's bits do not depend on which kernel computed it.
+template <typename C>
+__device__ __forceinline__ C diffuse(C c, C xm, C xp, C ym, C yp, C zm, C zp, C ci, C a, C rx,
+                                     C ry, C rz)
+{
+    C d2x = (xp - c) - (c - xm);
+    C d2y = (yp - c) - (c - ym);
+    C d2z = (zp - c) - (c - zm);
+    C lap = fma_(d2z, rz, fma_(d2y, ry, d2x * rx));
+    return fma_(a * ci, lap, c);
+}
+
+// Second-difference sum sum_d d2_d(v)/dd^2 (used by the adjoint).
+template <typename C>
+__device__ __forceinline__ C laplace(C c, C xm, C xp, C ym, C yp, C zm, C zp, C rx, C ry, C rz)
+{
+    C d2x = (xp - c) - (c - xm);
+    C d2y = (yp - c) - (c - ym);
+    C d2z = (zp - c) - (c - zm);
+    return fma_(d2z, rz, fma_(d2y, ry, d2x * rx));
+}
+
+// ------------------------------------------------------------------ hash
+// PCG hash of Jarzynski and Olano, "Hash Functions for GPU Rendering",
+// JCGT 9(3), 2020: one LCG step of O'Neill's PCG followed by its RXS-M-XS
+// output permutation; a bijection of 32-bit words.
+__host__ __device__ __forceinline__ uint32_t pcg_hash(uint32_t v)
+{
+    uint32_t state = v * 747796405u + 2891336453u;
+    uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+    return (word >> 22u) ^ word;
+}
+
+// Key of one plane k for the key of a (seed, counter) pair.
+__device__ __forceinline__ uint32_t plane_key(uint32_t key, int k) { return pcg_hash(key + (uint32_t)k); }
+
+// Random word of point (i, j) in a plane with key pk.
+__device__ __forceinline__ uint32_t point_bits(uint32_t pk, int i, int j, int nx)
+{
+    return pcg_hash(pk ^ (uint32_t)(i + nx * j));
+}
+
+// ---------------------------------------------------- FP16 stores
+// Unbiased stochastic rounding of a float to FP16: x is rounded up to the
+// next FP16 value with probability equal to its distance from the lower one
+// divided by their spacing.  In the FP16 normal range that is adding 13
+// uniform bits below the FP16 ulp to the magnitude and truncating (an FP16
+// value has 13 fewer fraction bits than a float); in the subnormal range the
+// spacing is 2^-24 and the comparison is done on the scaled value.  Values
+// already representable in FP16 are returned unchanged.
+__device__ __forceinline__ _Float16 round_sr(float x, uint32_t r)
+{
+    float ax = __builtin_fabsf(x);
+    if (!(ax < 65504.0f)) return (_Float16)x;  // overflow, inf, nan
+    if (ax >= 6.103515625e-05f) {              // 2^-14, smallest FP16 normal
+        uint32_t b = __float_as_uint(x);
+        b = (b + (r & 0x1FFFu)) & ~0x1FFFu;
+        return (_Float16)__uint_as_float(b);
+    }
+    float s = ax * 16777216.0f;  // exact: multiples of 2^-24 become integers
+    float f = __builtin_floorf(s);
+    float u = (float)(r >> 8) * (1.0f / 16777216.0f);
+    float m = (u < s - f) ? f + 1.0f : f;
+    return (_Float16)__builtin_copysignf(m * 5.9604644775390625e-08f, x);
+}
+
+template <typename S> struct Store {
+    template <typename C> __device__ __forceinline__ static S put(C v, uint32_t, int) { return (S)v; }
+};
+template <> struct Store<_Float16> {
+    __device__ __forceinline__ static _Float16 put(float v, uint32_t r, int stochastic)
+    {
+        return stochastic ? round_sr(v, r) : (_Float16)v;
+    }
+};
+
+// ------------------------------------------------------------------ boxes
+// Half-open index box [i0,i1) x [j0,j1) x [k0,k1).
+struct Box {
+    int i0, i1, j0, j1, k0, k1;
+};
+
+// Up to 6 boxes walked by one launch.  Each box's rows (j,k) are cut into
+// segments of `lpr` lanes (a power of two, >= the box width up to 64), so a
+// 15-point-wide slab packs four rows into one 64-lane wavefront.
+struct BoxSet {
+    Box b[6];
+    int lpr_log2[6];
+    int nseg_x[6];   // segments per row
+    int64_t first[7];  // first thread of each box (prefix sum), first[n] = total
+    int n;
+};
+
+// Map a global thread index to a point of a box set; returns false for
+// threads past the end or lanes past a row segment's end.
+__device__ __forceinline__ bool boxset_point(const BoxSet &bs, int64_t t, int &i, int &j, int &k)
+{
+    int b = 0;
+#pragma unroll
+    for (int q = 1; q < 6; ++q)
+        if (q < bs.n && t >= bs.first[q]) b = q;
+    if (t >= bs.first[bs.n]) return false;
+    const Box &bx = bs.b[b];
+    int64_t local = t - bs.first[b];
+    int lane = (int)(local & ((1 << bs.lpr_log2[b]) - 1));
+    int64_t seg = local >> bs.lpr_log2[b];
+    int sx = (int)(seg % bs.nseg_x[b]);
+    int64_t row = seg / bs.nseg_x[b];
+    int h = bx.j1 - bx.j0;
+    i = bx.i0 + (sx << bs.lpr_log2[b]) + lane;
+    j = bx.j0 + (int)(row % h);
+    k = bx.k0 + (int)(row / h);
+    return i < bx.i1;
+}
+
+// ------------------------------------------------------------ XCD mapping
+// Work-groups of one launch are handed to the 8 XCDs (each with its own L2)
+// in turn: group g runs on XCD g % 8.  Renumber them so each XCD receives
+// one contiguous range of logical tiles; tiles that share halo rows then
+// share an L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t g, int64_t n)
+{
+    const int64_t X = 8;
+    int64_t q = n / X, r = n % X;
+    int64_t x = g % X, slot = g / X;
+    return (x < r) ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
+}
+
+}  // namespace igg

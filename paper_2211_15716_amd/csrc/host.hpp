@@ -1,0 +1,128 @@
+// host.hpp -- host-side state of the implicit global grid and the launchers
+// each kernel file provides to the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "igg.h"
+#include "device.hpp"
+
+namespace igg {
+
+// ------------------------------------------------------------------ errors
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+#define IGG_HIP(call)                                        \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return ::igg::hip_fail(e_, #call); \
+    } while (0)
+
+// ------------------------------------------------------------------ state
+// The one implicit global grid of the process (the paper's calls take no
+// handle).  Device resources are created on first GPU use.
+struct Grid {
+    bool init = false;
+    int n[3] = {0, 0, 0};
+    int dims[3] = {1, 1, 1};
+    int periods[3] = {0, 0, 0};
+    int ol[3] = {2, 2, 2};
+
+    bool dev_ready = false;
+    int device = -1;
+    hipStream_t side = nullptr;       // helper stream: boundary slabs + halo chain
+    hipEvent_t ev_fork = nullptr;     // caller stream -> helper stream
+    hipEvent_t ev_join = nullptr;     // helper stream -> caller stream
+
+    unsigned char *halo_buf = nullptr;  // send and receive planes
+    size_t halo_cap = 0;                // bytes of one side of one field (one plane)
+
+    double *red_part = nullptr;  // per-block partial results
+    double *red_host = nullptr;  // pinned host result
+
+    bool timing = false;
+    std::vector<hipEvent_t> tev;  // start/stop pairs of timed launches
+    size_t tev_used = 0;
+    int64_t t_launches = 0, t_points = 0;
+    double t_ms = 0.0;
+};
+
+Grid &grid();
+int ensure_device();  // create stream, events, buffers on the current device
+
+// ------------------------------------------------------------ validation
+int check_field(const igg_field *f, const char *name, bool grid_sized);
+int64_t field_elems(const igg_field &f);
+int elem_bytes(int dtype);
+bool overlaps_mem(const igg_field &a, const igg_field &b);
+
+// ------------------------------------------------------------ schedules
+struct Split {
+    Box boundary[6];
+    int nb = 0;
+    Box inner;
+};
+int plan_split(const int n[3], const int w[3], Split &s);
+BoxSet make_boxset(const Box *b, int nb);
+
+// ------------------------------------------------------------- launchers
+// Halo update of fields (already validated) on `s`.
+int launch_halo(const igg_field *f, int nf, hipStream_t s);
+
+struct StepArgs {
+    void *T2;
+    const void *T;
+    const void *Ci;
+    int nx, ny, nz;
+    double a, rx, ry, rz;  // dt*lam, 1/dx^2, 1/dy^2, 1/dz^2
+    uint32_t key;          // FP16 stochastic-rounding key
+    int stochastic;
+};
+int launch_step_boxes(int dtype, const StepArgs &a, const Box *b, int nb, hipStream_t s);
+int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s);
+
+struct AdjArgs {
+    void *lam_n;
+    const void *lp;
+    const void *Tn;
+    const void *Ci;
+    void *gCi;
+    int nx, ny, nz;
+    double a, rx, ry, rz;
+};
+int launch_adjoint_boxes(int dtype, const AdjArgs &a, const Box *b, int nb, hipStream_t s);
+int launch_adjoint_inner(int dtype, const AdjArgs &a, const Box &b, hipStream_t s);
+
+struct FluxArgs {
+    void *qx, *qy, *qz;
+    const void *T;
+    void *T2;
+    const void *Ci;
+    int nx, ny, nz;
+    double lam, dt, rdx, rdy, rdz;
+};
+int launch_flux(int dtype, const FluxArgs &a, hipStream_t s);
+int launch_flux_update(int dtype, const FluxArgs &a, hipStream_t s);
+
+struct FluxAdjArgs {
+    void *lam_n;
+    const void *lp;
+    const void *Ci;
+    const void *qx, *qy, *qz;
+    void *px, *py, *pz;
+    void *gCi;
+    int nx, ny, nz;
+    double lam, dt, rdx, rdy, rdz;
+};
+int launch_flux_adjoint(int dtype, const FluxAdjArgs &a, hipStream_t s);
+
+int launch_reduce(int op, const igg_field &a, const igg_field *b, double *out, hipStream_t s);
+
+// FP16 stochastic-rounding key of a (seed, counter) pair.
+uint32_t sr_key(uint64_t seed, uint64_t counter);
+
+}  // namespace igg
