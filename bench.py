@@ -1,0 +1,300 @@
+"""Benchmark of the explicit 3-D diffusion step with periodic halo update on
+one MI355X.
+
+Workload (value): 512^3 FP64 local grid, 1x1x1 periodic topology, overlap 2,
+lam = 1, dx = 1/(n-1), T0 = 1.7 + Gaussian bump, Ci lognormal(log 0.5, 0.2)
+from seed 0, dt from maximum(Ci); every step is diffusion_step with
+boundary-first split (16, 2, 2): boundary slabs and the halo update
+(pack, exchange, unpack of T2) on the helper stream, the inner region on the
+caller stream.  A step = one such call; K steps are timed after W warm-up
+steps, with inputs already resident in HBM.
+
+value = T_eff = (bytes of T read + Ci read + T2 written, each once per point)
+/ time per step, in GB/s (decimal).
+
+Also reported on the same line:
+  roofline      the inner-region step kernel: algorithmic bytes per launch
+                over its average duration, timed live with HIP events on the
+                stream it runs on, against the 8 TB/s HBM3E peak;
+  cpu_baseline  the CPU oracle on the host cores: 100 steps of the same
+                512^3 workload (bounded to about 10-30 s), as T_eff;
+  variants      FP32 and FP16-storage steps at 512^3 (noisy-bump recipe,
+                uniform Ci) with their error against the FP64 result, the
+                unsplit FP64 step, and the checkpointed adjoint.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "T_eff GB/s & % HBM peak per step, 512^3 FP64 vs FP32 fwd, and adjoint"
+HBM_PEAK_GBS = 8000.0
+SPLIT = (16, 2, 2)
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=100)
+    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--n", type=int, default=512, help="cube edge of the headline workload")
+    p.add_argument("--no-variants", action="store_true", help="headline FP64 run only")
+    p.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    p.add_argument("--profile", action="store_true",
+                   help="headline loop only, for running under rocprofv3")
+    return p.parse_args()
+
+
+def kernel_source_hash():
+    """Hash of the sources the inner step kernel is built from."""
+    h = hashlib.sha256()
+    for f in ("step.hip", "device.hpp"):
+        with open(os.path.join(ROOT, "paper_2211_15716_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_hash, key):
+    """HBM bytes per launch measured by rocprofv3 PMC runs, if they were taken
+    on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = rec.get(key)
+    if not e or e.get("kernel_source_hash") != kernel_hash:
+        return None
+    return e.get("bytes_per_launch")
+
+
+def time_steps(igg, torch, T, W, C, lam, dt, dx, dy, dz, steps, warmup, split, rnd_seed=None):
+    """Warm up, then time `steps` diffusion steps; returns (ms/step, final
+    buffer, inner-kernel ms/launch, inner points/launch)."""
+    a, b = T, W
+
+    def one(it):
+        nonlocal a, b
+        rnd = igg.rounding("stochastic", rnd_seed, it) if rnd_seed is not None else None
+        igg.diffusion_step(b, a, C, lam, dt, dx, dy, dz, split=split, rnd=rnd)
+        a, b = b, a
+
+    for it in range(warmup):
+        one(it)
+    torch.cuda.synchronize()
+    igg.timing_read()  # discard
+    igg.timing_enable(True)
+    s0 = torch.cuda.Event(enable_timing=True)
+    s1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s0.record()
+    for it in range(warmup, warmup + steps):
+        one(it)
+    s1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    igg.timing_enable(False)
+    k_ms, k_launches, k_points = igg.timing_read()
+    ev_ms = s0.elapsed_time(s1)
+    ms = max(wall * 1e3, ev_ms) / steps
+    per_launch = k_ms / max(1, k_launches)
+    return ms, a, per_launch, (k_points // max(1, k_launches))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this library has no multi-GPU path "
+              "(the halo exchange is a self-exchange on a 1x1x1 periodic topology); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2211_15716_amd import igg, synth
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+    n = args.n
+    K, Wm = args.steps, args.warmup
+
+    # ---------------------------------------------------------------- headline FP64
+    log(f"generating {n}^3 FP64 inputs (bump + lognormal Ci, seed 0)")
+    w = synth.workload("c2_512_fp64", seed=0, n=n)
+    lam, dx, dy, dz = w["lam"], w["dx"], w["dy"], w["dz"]
+    pts = n ** 3
+    igg.init_global_grid(n, n, n, dims=(1, 1, 1), periods=(1, 1, 1), overlaps=(2, 2, 2))
+    T = torch.from_numpy(w["T0"]).cuda()
+    C = torch.from_numpy(w["Ci"]).cuda()
+    igg.update_halo(T, C)
+    T0_dev = T.clone()
+    dt = igg.diffusion_dt(C, lam, dx, dy, dz)
+    Wb = torch.empty_like(T)
+    log(f"timing {K} FP64 steps after {Wm} warm-up steps, split {SPLIT}")
+    ms, out64, k_ms, k_pts = time_steps(igg, torch, T, Wb, C, lam, dt, dx, dy, dz, K, Wm, SPLIT)
+    teff = 24.0 * pts / (ms * 1e-3) / 1e9
+    k_bytes = 24.0 * k_pts
+    k_gbs = k_bytes / (k_ms * 1e-3) / 1e9
+    khash = kernel_source_hash()
+    traffic = traffic_from_profiles(khash, "inner_step_f64_512")
+    halo_overhead = ms / (k_ms * pts / max(1, k_pts)) - 1.0 if k_ms > 0 else None
+    log(f"FP64: {ms:.4f} ms/step, T_eff {teff:.1f} GB/s; inner kernel {k_ms:.4f} ms, {k_gbs:.1f} GB/s")
+
+    result = {
+        "metric": METRIC, "value": round(teff, 2), "unit": "GB/s", "n_gpus": 1, "steps": K,
+        "warmup": Wm, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"explicit 3-D diffusion step + periodic halo update, {n}^3 FP64, "
+                               f"1x1x1 periodic topology, overlap 2, split {SPLIT}, bump T0, "
+                               f"lognormal Ci (seed 0)",
+                   "grid": [n, n, n], "nt_timed": K, "split": list(SPLIT), "dt": dt,
+                   "bytes_per_point": 24, "parallelism": "1 GPU"},
+        "hbm_frac": round(teff / HBM_PEAK_GBS, 4),
+        "roofline": {"bound": "hbm", "kernel": "k_step_zmarch<double> (inner region)",
+                     "achieved": round(k_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(k_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "bytes_per_launch": k_bytes, "points_per_launch": k_pts,
+                     "ms_per_launch": round(k_ms, 5), "kernel_source_hash": khash},
+        "halo_overhead": None if halo_overhead is None else round(halo_overhead, 4),
+    }
+
+    if args.profile:
+        print(json.dumps(result), flush=True)
+        igg.finalize_global_grid()
+        return
+
+    # ---------------------------------------------------------------- plain copy, the achievable ceiling
+    src = torch.empty(1 << 28, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    result["copy_probe_GBs"] = round(copy_gbs, 1)
+    log(f"plain device copy of 2 GiB: {copy_gbs:.1f} GB/s")
+    del src, dst
+
+    # ---------------------------------------------------------------- unsplit FP64 for comparison
+    T = T0_dev.clone()
+    ms_u, _, _, _ = time_steps(igg, torch, T, Wb, C, lam, dt, dx, dy, dz, min(K, 50), 5, None)
+    result["variants"] = {"f64_unsplit": {"ms_per_step": round(ms_u, 5),
+                                          "T_eff_GBs": round(24.0 * pts / (ms_u * 1e-3) / 1e9, 1)}}
+
+    # ---------------------------------------------------------------- CPU oracle baseline
+    gpu64 = None
+    if not args.no_cpu:
+        import oracle
+        oracle_nt = K if K <= 100 else 100
+        T0h, Cih = w["T0"].copy(), w["Ci"].copy()
+        oracle.halo(T0h)
+        oracle.halo(Cih)
+        # the GPU result after exactly oracle_nt steps, for a full-field error
+        T = T0_dev.clone()
+        ms_chk, gout, _, _ = time_steps(igg, torch, T, Wb, C, lam, dt, dx, dy, dz, oracle_nt, 0, SPLIT)
+        gpu64 = gout.cpu().numpy()
+        log(f"oracle: up to {oracle_nt} steps of the {n}^3 FP64 workload on the host")
+        cur, nxt = T0h, np.empty_like(T0h)
+        nxt[...] = cur
+        t0 = time.perf_counter()
+        done = 0
+        while done < oracle_nt:
+            oracle.step(cur, Cih, lam, dt, dx, dy, dz, out=nxt)
+            oracle.halo(nxt)
+            cur, nxt = nxt, cur
+            done += 1
+            if time.perf_counter() - t0 > 30.0:
+                break
+        el = time.perf_counter() - t0
+        cpu_teff = 24.0 * pts * done / el / 1e9
+        result["cpu_baseline"] = {"value": round(cpu_teff, 2), "unit": "GB/s", "cores": oracle.num_threads(),
+                                  "kind": "oracle",
+                                  "sample": f"{done} steps of the {n}^3 FP64 workload (plain C loops, "
+                                            f"OpenMP over z), {el:.1f} s"}
+        if done == oracle_nt:
+            err = oracle.rel_max_err(gpu64, cur)
+            result["f64_err_vs_oracle"] = err
+            log(f"FP64 GPU vs oracle after {done} steps: {err:.3e}")
+        del T0h, Cih, cur, nxt
+
+    if args.no_variants:
+        print(json.dumps(result), flush=True)
+        igg.finalize_global_grid()
+        return
+
+    # ---------------------------------------------------------------- FP32 / FP16 variants
+    log(f"generating {n}^3 noisy-bump inputs (uniform Ci, seed 0) for the precision forms")
+    w3 = synth.workload("c3_512", seed=0, n=n)
+    T0_64 = torch.from_numpy(w3["T0"]).cuda()
+    C_64 = torch.from_numpy(w3["Ci"]).cuda()
+    igg.update_halo(T0_64, C_64)
+    dt3 = igg.diffusion_dt(C_64, lam, dx, dy, dz)
+    nt3 = 100
+    ref = None
+    for name, tdt in (("f64", torch.float64), ("f32", torch.float32), ("f16", torch.float16)):
+        Tv = T0_64.to(tdt).contiguous()
+        Cv = C_64.to(tdt).contiguous()
+        Wv = torch.empty_like(Tv)
+        seed = 1234 if name == "f16" else None
+        # error run: exactly nt3 steps
+        outv = Tv.clone()
+        a, b = outv, torch.empty_like(Tv)
+        for it in range(nt3):
+            rnd = igg.rounding("stochastic", seed, it) if seed is not None else None
+            igg.diffusion_step(b, a, Cv, lam, dt3, dx, dy, dz, split=SPLIT, rnd=rnd)
+            a, b = b, a
+        final = a.to(torch.float64)
+        if name == "f64":
+            ref = final
+            err = 0.0
+        else:
+            d = (final - ref)[1:-1, 1:-1, 1:-1].abs().max().item()
+            err = d / ref[1:-1, 1:-1, 1:-1].abs().max().item()
+        msv, _, kv_ms, kv_pts = time_steps(igg, torch, Tv.clone(), Wv, Cv, lam, dt3, dx, dy, dz, K, Wm, SPLIT,
+                                           rnd_seed=seed)
+        s = Tv.element_size()
+        entry = {"ms_per_step": round(msv, 5), "T_eff_GBs": round(3 * s * pts / (msv * 1e-3) / 1e9, 1),
+                 "hbm_frac": round(3 * s * pts / (msv * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                 "inner_kernel_GBs": round(3 * s * kv_pts / (kv_ms * 1e-3) / 1e9, 1),
+                 "err_vs_f64": err, "nt_err": nt3}
+        if name == "f16":
+            entry["rounding"] = "stochastic"
+        result["variants"][name] = entry
+        log(f"{name}: {msv:.4f} ms/step, err vs FP64 {err:.3e}")
+        del Tv, Cv, Wv, outv, a, b, final
+    f32 = result["variants"]["f32"]
+    result["variants"]["f32_speedup_vs_f64"] = round(result["variants"]["f64"]["ms_per_step"] / f32["ms_per_step"], 3)
+    # FP16 with round-to-nearest stores, for comparison of the error
+    Tv = T0_64.to(torch.float16).contiguous()
+    Cv = C_64.to(torch.float16).contiguous()
+    a, b = Tv, torch.empty_like(Tv)
+    for it in range(nt3):
+        igg.diffusion_step(b, a, Cv, lam, dt3, dx, dy, dz, split=SPLIT)
+        a, b = b, a
+    d = (a.to(torch.float64) - ref)[1:-1, 1:-1, 1:-1].abs().max().item()
+    result["variants"]["f16"]["err_vs_f64_round_nearest"] = d / ref[1:-1, 1:-1, 1:-1].abs().max().item()
+    del Tv, Cv, a, b, T0_64, C_64, ref
+    torch.cuda.empty_cache()
+
+    print(json.dumps(result), flush=True)
+    igg.finalize_global_grid()
+
+
+if __name__ == "__main__":
+    main()
