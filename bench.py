@@ -52,6 +52,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     p.add_argument("--profile", action="store_true",
                    help="headline loop only, for running under rocprofv3")
+    p.add_argument("--split", default="16,2,2",
+                   help="boundary widths of the timed steps, or 'none' for the unsplit schedule")
     return p.parse_args()
 
 
@@ -81,7 +83,8 @@ def traffic_from_profiles(kernel_hash, key):
 
 def time_steps(igg, torch, T, W, C, lam, dt, dx, dy, dz, steps, warmup, split, rnd_seed=None):
     """Warm up, then time `steps` diffusion steps; returns (ms/step, final
-    buffer, inner-kernel ms/launch, inner points/launch)."""
+    buffer, inner-kernel ms/launch, inner points/launch, boundary-kernel ms
+    per step)."""
     a, b = T, W
 
     def one(it):
@@ -106,11 +109,11 @@ def time_steps(igg, torch, T, W, C, lam, dt, dx, dy, dz, steps, warmup, split, r
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     igg.timing_enable(False)
-    k_ms, k_launches, k_points = igg.timing_read()
+    k_ms, k_launches, k_points, b_ms = igg.timing_read()
     ev_ms = s0.elapsed_time(s1)
     ms = max(wall * 1e3, ev_ms) / steps
     per_launch = k_ms / max(1, k_launches)
-    return ms, a, per_launch, (k_points // max(1, k_launches))
+    return ms, a, per_launch, (k_points // max(1, k_launches)), b_ms / steps
 
 
 def main():
@@ -142,14 +145,17 @@ def main():
     T0_dev = T.clone()
     dt = igg.diffusion_dt(C, lam, dx, dy, dz)
     Wb = torch.empty_like(T)
-    log(f"timing {K} FP64 steps after {Wm} warm-up steps, split {SPLIT}")
-    ms, out64, k_ms, k_pts = time_steps(igg, torch, T, Wb, C, lam, dt, dx, dy, dz, K, Wm, SPLIT)
+    log(f"timing {K} FP64 steps after {Wm} warm-up steps, split {args.split}")
+    split = None if args.split == "none" else tuple(int(v) for v in args.split.split(","))
+    ms, out64, k_ms, k_pts, b_ms = time_steps(igg, torch, T, Wb, C, lam, dt, dx, dy, dz, K, Wm, split)
     teff = 24.0 * pts / (ms * 1e-3) / 1e9
     k_bytes = 24.0 * k_pts
     k_gbs = k_bytes / (k_ms * 1e-3) / 1e9
     khash = kernel_source_hash()
     traffic = traffic_from_profiles(khash, "inner_step_f64_512")
-    halo_overhead = ms / (k_ms * pts / max(1, k_pts)) - 1.0 if k_ms > 0 else None
+    # the halo update runs beside the inner kernel: its cost is what the step
+    # takes beyond the boundary and inner kernels on the caller stream
+    halo_overhead = ms / (k_ms + b_ms) - 1.0 if (k_ms > 0 and split is not None) else None
     log(f"FP64: {ms:.4f} ms/step, T_eff {teff:.1f} GB/s; inner kernel {k_ms:.4f} ms, {k_gbs:.1f} GB/s")
 
     result = {
@@ -157,9 +163,9 @@ def main():
         "warmup": Wm, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"explicit 3-D diffusion step + periodic halo update, {n}^3 FP64, "
-                               f"1x1x1 periodic topology, overlap 2, split {SPLIT}, bump T0, "
+                               f"1x1x1 periodic topology, overlap 2, split {args.split}, bump T0, "
                                f"lognormal Ci (seed 0)",
-                   "grid": [n, n, n], "nt_timed": K, "split": list(SPLIT), "dt": dt,
+                   "grid": [n, n, n], "nt_timed": K, "split": None if split is None else list(split), "dt": dt,
                    "bytes_per_point": 24, "parallelism": "1 GPU"},
         "hbm_frac": round(teff / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "kernel": "k_step_zmarch<double> (inner region)",
@@ -168,6 +174,7 @@ def main():
                      "bytes_per_launch": k_bytes, "points_per_launch": k_pts,
                      "ms_per_launch": round(k_ms, 5), "kernel_source_hash": khash},
         "halo_overhead": None if halo_overhead is None else round(halo_overhead, 4),
+        "boundary_ms_per_step": round(b_ms, 5),
     }
 
     if args.profile:
@@ -193,7 +200,7 @@ def main():
 
     # ---------------------------------------------------------------- unsplit FP64 for comparison
     T = T0_dev.clone()
-    ms_u, _, _, _ = time_steps(igg, torch, T, Wb, C, lam, dt, dx, dy, dz, min(K, 50), 5, None)
+    ms_u, _, _, _, _ = time_steps(igg, torch, T, Wb, C, lam, dt, dx, dy, dz, min(K, 50), 5, None)
     result["variants"] = {"f64_unsplit": {"ms_per_step": round(ms_u, 5),
                                           "T_eff_GBs": round(24.0 * pts / (ms_u * 1e-3) / 1e9, 1)}}
 
@@ -207,7 +214,7 @@ def main():
         oracle.halo(Cih)
         # the GPU result after exactly oracle_nt steps, for a full-field error
         T = T0_dev.clone()
-        ms_chk, gout, _, _ = time_steps(igg, torch, T, Wb, C, lam, dt, dx, dy, dz, oracle_nt, 0, SPLIT)
+        ms_chk, gout, _, _, _ = time_steps(igg, torch, T, Wb, C, lam, dt, dx, dy, dz, oracle_nt, 0, SPLIT)
         gpu64 = gout.cpu().numpy()
         log(f"oracle: up to {oracle_nt} steps of the {n}^3 FP64 workload on the host")
         cur, nxt = T0h, np.empty_like(T0h)
@@ -266,7 +273,7 @@ def main():
         else:
             d = (final - ref)[1:-1, 1:-1, 1:-1].abs().max().item()
             err = d / ref[1:-1, 1:-1, 1:-1].abs().max().item()
-        msv, _, kv_ms, kv_pts = time_steps(igg, torch, Tv.clone(), Wv, Cv, lam, dt3, dx, dy, dz, K, Wm, SPLIT,
+        msv, _, kv_ms, kv_pts, _ = time_steps(igg, torch, Tv.clone(), Wv, Cv, lam, dt3, dx, dy, dz, K, Wm, SPLIT,
                                            rnd_seed=seed)
         s = Tv.element_size()
         entry = {"ms_per_step": round(msv, 5), "T_eff_GBs": round(3 * s * pts / (msv * 1e-3) / 1e9, 1),
@@ -292,8 +299,62 @@ def main():
     del Tv, Cv, a, b, T0_64, C_64, ref
     torch.cuda.empty_cache()
 
-    print(json.dumps(result), flush=True)
     igg.finalize_global_grid()
+
+    # ---------------------------------------------------------------- checkpointed adjoint
+    result["variants"]["adjoint_256"] = adjoint_variant(igg, torch, synth)
+
+    print(json.dumps(result), flush=True)
+
+
+def adjoint_variant(igg, torch, synth):
+    """Loss and gradient of the 256^3 FP64 inverse problem: nt = 200 steps,
+    T_obs from Ci_true (sine), guess Ci = 0.5, snapshots every 16 steps.
+    Algorithmic bytes: 24 per point per forward step (forward sweep and
+    recomputation) and 48 per point per adjoint step (lam', Ci, T_n read,
+    gCi read and written, lam written)."""
+    from paper_2211_15716_amd import diffusion
+    w = synth.workload("c4_256_inverse", seed=0)
+    n = w["nx"]
+    nt = w["nt"]
+    pts = n ** 3
+    igg.init_global_grid(n, n, n, dims=(1, 1, 1), periods=(1, 1, 1), overlaps=(2, 2, 2))
+    T, Ctrue = diffusion.prepare_fields(w["T0"], w["Ci"])
+    dt = igg.diffusion_dt(Ctrue, w["lam"], w["dx"], w["dy"], w["dz"])
+    prob = diffusion.Problem(w["lam"], dt, w["dx"], w["dy"], w["dz"], split=SPLIT)
+    O = diffusion.forward(T.clone(), Ctrue, nt, prob.lam, dt, prob.dx, prob.dy, prob.dz, split=SPLIT)
+    C = torch.full_like(T, 0.5)
+    sched = ("periodic", 16)
+    diffusion.loss_and_grad(T, C, O, prob, nt, sched)  # warm-up
+    torch.cuda.synchronize()
+    igg.timing_enable(True)
+    t0 = time.perf_counter()
+    L, gT, gC, sw = diffusion.loss_and_grad(T, C, O, prob, nt, sched)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    igg.timing_enable(False)
+    k_ms, k_launches, k_pts, b_ms = igg.timing_read()
+    nbytes = (24.0 * sw.advances + 48.0 * sw.adjoints) * pts
+    # the forward sweep alone, to split the time
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sw2 = diffusion.Sweep(prob, C, T, diffusion.checkpoint_ops(*sched[:1], nt, *sched[1:]))
+    sw2.forward(nt)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t1
+    rev_ms = (el - fwd) * 1e3 / nt
+    rev_bytes = (72.0 * pts)
+    out = {"grid": [n, n, n], "nt": nt, "schedule": "periodic every 16", "ms_total": round(el * 1e3, 3),
+           "forward_steps": sw.advances, "adjoint_steps": sw.adjoints, "peak_snapshots": sw.peak,
+           "T_eff_GBs": round(nbytes / el / 1e9, 1), "hbm_frac": round(nbytes / el / 1e9 / HBM_PEAK_GBS, 4),
+           "ms_per_reverse_step": round(rev_ms, 4),
+           "reverse_step_T_eff_GBs": round(rev_bytes / (rev_ms * 1e-3) / 1e9, 1),
+           "loss": L}
+    log(f"adjoint 256^3: {el*1e3:.1f} ms, T_eff {out['T_eff_GBs']} GB/s, reverse step {rev_ms:.4f} ms")
+    del T, Ctrue, O, C, gT, gC, sw, sw2
+    torch.cuda.empty_cache()
+    igg.finalize_global_grid()
+    return out
 
 
 if __name__ == "__main__":

@@ -114,9 +114,12 @@ int igg_topology(int n[3], int dims[3], int periods[3], int overlaps[3], int coo
 /* Halo update of up to IGG_MAX_FIELDS fields (Fig. 1 `update_halo!`, Sec. 2).
  * For each dimension in the order x, y, z, and each periodic one: pack the
  * planes ol_A-1 and n_A-ol_A of every field into send buffers, exchange them
- * with the neighbours (here the process itself: the upper neighbour receives
- * plane ol_A-1, the lower one plane n_A-ol_A), and unpack them into planes
- * n_A-1 and 0.  Full planes move, so edges and corners come out right.
+ * with the neighbours (the lower neighbour receives plane ol_A-1 into its
+ * last plane, the upper one plane n_A-ol_A into its first plane; here both
+ * neighbours are the process itself), and unpack them into planes n_A-1 and
+ * 0.  Full planes move, so edges and corners come out right.
+ * With the process as its own neighbour the three phases of a dimension run
+ * in one launch, each thread carrying its elements through all three.
  * A field may have the grid size n or n+1 per dimension (staggered faces);
  * its overlap is then ol_A = ol + (n_A - n).  Non-periodic dimensions are
  * left as they are.  Fields may have different element types.
@@ -140,9 +143,9 @@ int igg_finalize_global_grid(void);
  * element type; T must carry a valid halo (the previous step's update).
  *   split  boundary widths (Fig. 1 `@hide_communication (16, 2, 2)`), counted
  *          from the array edge including the halo plane, each >= overlap.
- *          The boundary slabs are computed first on the library's helper
- *          stream, then the halo of T2 is updated there, while the inner
- *          region runs on `stream`; `stream` then waits for the helper.
+ *          The boundary slabs are computed first on `stream`; then the halo
+ *          update of T2 runs on the library's helper stream while the inner
+ *          region runs on `stream`, which finally waits for the helper.
  *          NULL = no overlap: everything runs on `stream` in order.
  *   rnd    FP16 store rounding, NULL = round to nearest even (ignored for
  *          FP64/FP32).
@@ -218,13 +221,17 @@ int igg_reduce(int op, const igg_field *a, const igg_field *b, double *out, void
  * written.  Pure host function.  Errors: IGG_ERR_ARG. */
 int igg_plan_split(const int n[3], const int split[3], int boxes[7][6], int *nboxes);
 
-/* Kernel timing of the dominant kernel.  While enabled, each launch of the
- * inner-region step kernel is bracketed by two HIP events on the stream it
- * runs on; igg_timing_read synchronises those events and returns the summed
- * duration in milliseconds, the launch count and the number of inner points
- * those launches computed, then resets the totals.  Errors: IGG_ERR_HIP. */
+/* Kernel timing.  While enabled, each launch of the inner-region kernel of
+ * diffusion_step / diffusion_step_adjoint (and the cell update of
+ * diffusion_flux_step) is bracketed by two HIP events on the stream it runs
+ * on, and so are the boundary-slab kernels of a split step.
+ * igg_timing_read synchronises those events and returns the summed
+ * inner-kernel duration in milliseconds, its launch count, the inner points
+ * those launches computed, and the summed boundary-kernel duration (any
+ * pointer may be NULL), then resets the totals.  Errors: IGG_ERR_STATE,
+ * IGG_ERR_HIP. */
 int igg_timing_enable(int on);
-int igg_timing_read(double *ms, int64_t *launches, int64_t *points);
+int igg_timing_read(double *ms, int64_t *launches, int64_t *points, double *boundary_ms);
 
 /* Message for the calling thread's last failure ("" if none). */
 const char *igg_last_error(void);

@@ -50,10 +50,11 @@ void oracle_set_num_threads(int n)
 
 /*
  * Halo update of one field on a single-process grid (Fig. 1 `update_halo!`,
- * Sec. 2).  With one process, a periodic dimension is its own neighbour on
- * both sides: the plane at index ol-1 is what the upper neighbour receives
- * into its last plane, and the plane at index n-ol is what the lower
- * neighbour receives into its first plane.  Dimensions are processed in the
+ * Sec. 2).  Neighbouring local grids share ol planes, so plane ol-1 is the
+ * last plane of the lower neighbour and plane n-ol the first plane of the
+ * upper one; with one process, a periodic dimension is its own neighbour on
+ * both sides and the halo planes take plane ol-1 (last plane) and plane n-ol
+ * (first plane) of the same array.  Dimensions are processed in the
  * order x, y, z and each copy moves the full plane, so edge and corner halo
  * points end up as images in every periodic dimension.  A non-periodic
  * dimension has no neighbour and is left untouched.

@@ -50,7 +50,7 @@ def build(verbose=False, jobs=8):
         objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + \
-        ["-Wl,-rpath,/opt/rocm/lib"]
+        ["-Wl,-rpath,/opt/rocm/lib", "-Wl,--no-undefined"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -3,6 +3,7 @@
 // boundary-first schedule of the step.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -80,16 +81,19 @@ int plan_split(const int n[3], const int w[3], Split &s)
     int kz0 = std::min(w[2], n[2] - 1), kz1 = std::max(n[2] - w[2], kz0);
     int jy0 = std::min(w[1], n[1] - 1), jy1 = std::max(n[1] - w[1], jy0);
     int ix0 = std::min(w[0], n[0] - 1), ix1 = std::max(n[0] - w[0], ix0);
-    auto add = [&](int i0, int i1, int j0, int j1, int k0, int k1) {
-        if (i0 < i1 && j0 < j1 && k0 < k1) s.boundary[s.nb++] = Box{i0, i1, j0, j1, k0, k1};
+    auto add = [&](int kind, int i0, int i1, int j0, int j1, int k0, int k1) {
+        if (i0 < i1 && j0 < j1 && k0 < k1) {
+            s.kind[s.nb] = kind;
+            s.boundary[s.nb++] = Box{i0, i1, j0, j1, k0, k1};
+        }
     };
     const int X = n[0] - 1, Y = n[1] - 1, Z = n[2] - 1;
-    add(1, X, 1, Y, 1, kz0);        // z low slab
-    add(1, X, 1, Y, kz1, Z);        // z high slab
-    add(1, X, 1, jy0, kz0, kz1);    // y low slab
-    add(1, X, jy1, Y, kz0, kz1);    // y high slab
-    add(1, ix0, jy0, jy1, kz0, kz1);  // x low slab
-    add(ix1, X, jy0, jy1, kz0, kz1);  // x high slab
+    add(1, 1, X, 1, Y, 1, kz0);        // z low slab
+    add(1, 1, X, 1, Y, kz1, Z);        // z high slab
+    add(1, 1, X, 1, jy0, kz0, kz1);    // y low slab
+    add(1, 1, X, jy1, Y, kz0, kz1);    // y high slab
+    add(0, 1, ix0, jy0, jy1, kz0, kz1);  // x low slab
+    add(0, ix1, X, jy0, jy1, kz0, kz1);  // x high slab
     s.inner = Box{ix0, ix1, jy0, jy1, kz0, kz1};
     return IGG_OK;
 }
@@ -170,8 +174,9 @@ static int release_device()
     return rc;
 }
 
-// Bracket a launch on stream s with timing events when timing is enabled.
-static int timing_mark(hipStream_t s)
+// Bracket a launch on stream s with timing events when timing is enabled;
+// kind 0 marks the inner-region kernel, kind 1 the boundary kernels.
+static int timing_mark(hipStream_t s, int kind)
 {
     Grid &g = grid();
     if (!g.timing) return IGG_OK;
@@ -179,7 +184,9 @@ static int timing_mark(hipStream_t s)
         hipEvent_t e;
         IGG_HIP(hipEventCreate(&e));
         g.tev.push_back(e);
+        g.tev_kind.push_back(0);
     }
+    g.tev_kind[g.tev_used] = kind;
     IGG_HIP(hipEventRecord(g.tev[g.tev_used++], s));
     return IGG_OK;
 }
@@ -253,8 +260,11 @@ int igg_init_global_grid(int nx, int ny, int nz, const int dims[3], const int pe
     }
     g.init = true;
     g.timing = false;
+    {
+        const char *e = getenv("IGG_SCHEDULE");
+        g.schedule = (e && *e) ? atoi(e) : 0;
+    }
     g.tev_used = 0;
-    g.t_ms = 0;
     g.t_launches = g.t_points = 0;
     if (me) *me = 0;
     return IGG_OK;
@@ -366,23 +376,39 @@ int diffusion_step(const igg_field *T2, const igg_field *T, const igg_field *Ci,
                dt * lam, 1.0 / (dx * dx), 1.0 / (dy * dy), 1.0 / (dz * dz), key, stochastic};
     if (!split) {
         Box all{1, g.n[0] - 1, 1, g.n[1] - 1, 1, g.n[2] - 1};
-        if ((rc = timing_mark(s))) return rc;
+        if ((rc = timing_mark(s, 0))) return rc;
         if ((rc = launch_step_inner(T->dtype, a, all, s))) return rc;
-        if ((rc = timing_mark(s))) return rc;
+        if ((rc = timing_mark(s, 0))) return rc;
         if (g.timing) { g.t_launches++; g.t_points += box_points(all); }
         return launch_halo(T2, 1, s);
     }
+    // boundary first: the slabs on the caller stream, then the halo update of
+    // T2 on the helper stream while the inner region runs on the caller stream
     Split sp;
     plan_split(g.n, split, sp);
+    const int sched = g.schedule;
+    Split main_part = sp, side_part = sp;
+    main_part.nb = side_part.nb = 0;
+    for (int q = 0; q < sp.nb; ++q) {
+        bool on_side = sched == 1 || (sched == 2 && sp.kind[q] == 0);
+        Split &dst = on_side ? side_part : main_part;
+        dst.boundary[dst.nb] = sp.boundary[q];
+        dst.kind[dst.nb++] = sp.kind[q];
+    }
+    if (main_part.nb) {
+        if ((rc = timing_mark(s, 1))) return rc;
+        if ((rc = launch_step_boundary(T->dtype, a, main_part, s))) return rc;
+        if ((rc = timing_mark(s, 1))) return rc;
+    }
     IGG_HIP(hipEventRecord(g.ev_fork, s));
     IGG_HIP(hipStreamWaitEvent(g.side, g.ev_fork, 0));
-    if (sp.nb && (rc = launch_step_boxes(T->dtype, a, sp.boundary, sp.nb, g.side))) return rc;
+    if (side_part.nb && (rc = launch_step_boundary(T->dtype, a, side_part, g.side))) return rc;
     if ((rc = launch_halo(T2, 1, g.side))) return rc;
     IGG_HIP(hipEventRecord(g.ev_join, g.side));
     if (box_points(sp.inner) > 0) {
-        if ((rc = timing_mark(s))) return rc;
+        if ((rc = timing_mark(s, 0))) return rc;
         if ((rc = launch_step_inner(T->dtype, a, sp.inner, s))) return rc;
-        if ((rc = timing_mark(s))) return rc;
+        if ((rc = timing_mark(s, 0))) return rc;
         if (g.timing) { g.t_launches++; g.t_points += box_points(sp.inner); }
     }
     IGG_HIP(hipStreamWaitEvent(s, g.ev_join, 0));
@@ -438,23 +464,27 @@ int diffusion_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1,
               dt * lam, 1.0 / (dx * dx), 1.0 / (dy * dy), 1.0 / (dz * dz)};
     if (!split) {
         Box all{1, g.n[0] - 1, 1, g.n[1] - 1, 1, g.n[2] - 1};
-        if ((rc = timing_mark(s))) return rc;
+        if ((rc = timing_mark(s, 0))) return rc;
         if ((rc = launch_adjoint_inner(dt_, a, all, s))) return rc;
-        if ((rc = timing_mark(s))) return rc;
+        if ((rc = timing_mark(s, 0))) return rc;
         if (g.timing) { g.t_launches++; g.t_points += box_points(all); }
         return launch_halo(lam_n, 1, s);
     }
     Split sp;
     plan_split(g.n, split, sp);
+    if (sp.nb) {
+        if ((rc = timing_mark(s, 1))) return rc;
+        if ((rc = launch_adjoint_boxes(dt_, a, sp.boundary, sp.nb, s))) return rc;
+        if ((rc = timing_mark(s, 1))) return rc;
+    }
     IGG_HIP(hipEventRecord(g.ev_fork, s));
     IGG_HIP(hipStreamWaitEvent(g.side, g.ev_fork, 0));
-    if (sp.nb && (rc = launch_adjoint_boxes(dt_, a, sp.boundary, sp.nb, g.side))) return rc;
     if ((rc = launch_halo(lam_n, 1, g.side))) return rc;
     IGG_HIP(hipEventRecord(g.ev_join, g.side));
     if (box_points(sp.inner) > 0) {
-        if ((rc = timing_mark(s))) return rc;
+        if ((rc = timing_mark(s, 0))) return rc;
         if ((rc = launch_adjoint_inner(dt_, a, sp.inner, s))) return rc;
-        if ((rc = timing_mark(s))) return rc;
+        if ((rc = timing_mark(s, 0))) return rc;
         if (g.timing) { g.t_launches++; g.t_points += box_points(sp.inner); }
     }
     IGG_HIP(hipStreamWaitEvent(s, g.ev_join, 0));
@@ -503,9 +533,9 @@ int diffusion_flux_step(const igg_field *T2, const igg_field *T, const igg_field
     FluxArgs a{qx->data, qy->data, qz->data, T->data, T2->data, Ci->data, g.n[0], g.n[1], g.n[2],
                lam, dt, 1.0 / dx, 1.0 / dy, 1.0 / dz};
     if ((rc = launch_flux(ty, a, s))) return rc;
-    if ((rc = timing_mark(s))) return rc;
+    if ((rc = timing_mark(s, 0))) return rc;
     if ((rc = launch_flux_update(ty, a, s))) return rc;
-    if ((rc = timing_mark(s))) return rc;
+    if ((rc = timing_mark(s, 0))) return rc;
     if (g.timing) { g.t_launches++; g.t_points += (int64_t)(g.n[0] - 2) * (g.n[1] - 2) * (g.n[2] - 2); }
     igg_field hf[4] = {*T2, *qx, *qy, *qz};
     return launch_halo(hf, 4, s);
@@ -580,22 +610,22 @@ int igg_timing_enable(int on)
     return IGG_OK;
 }
 
-int igg_timing_read(double *ms, int64_t *launches, int64_t *points)
+int igg_timing_read(double *ms, int64_t *launches, int64_t *points, double *boundary_ms)
 {
     Grid &g = grid();
     if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
-    double total = g.t_ms;
+    double total[2] = {0.0, 0.0};
     for (size_t q = 0; q + 1 < g.tev_used; q += 2) {
         float t = 0.f;
         IGG_HIP(hipEventSynchronize(g.tev[q + 1]));
         IGG_HIP(hipEventElapsedTime(&t, g.tev[q], g.tev[q + 1]));
-        total += t;
+        total[g.tev_kind[q] ? 1 : 0] += t;
     }
-    if (ms) *ms = total;
+    if (ms) *ms = total[0];
+    if (boundary_ms) *boundary_ms = total[1];
     if (launches) *launches = g.t_launches;
     if (points) *points = g.t_points;
     g.tev_used = 0;
-    g.t_ms = 0;
     g.t_launches = g.t_points = 0;
     return IGG_OK;
 }

@@ -44,11 +44,13 @@ struct Grid {
     double *red_part = nullptr;  // per-block partial results
     double *red_host = nullptr;  // pinned host result
 
+    int schedule = 0;  // where the boundary slabs run (0: caller stream first)
+
     bool timing = false;
     std::vector<hipEvent_t> tev;  // start/stop pairs of timed launches
+    std::vector<int> tev_kind;    // 0: inner-region kernel, 1: boundary kernels
     size_t tev_used = 0;
     int64_t t_launches = 0, t_points = 0;
-    double t_ms = 0.0;
 };
 
 Grid &grid();
@@ -63,6 +65,7 @@ bool overlaps_mem(const igg_field &a, const igg_field &b);
 // ------------------------------------------------------------ schedules
 struct Split {
     Box boundary[6];
+    int kind[6];  // 0: x slab, 1: y or z slab
     int nb = 0;
     Box inner;
 };
@@ -84,6 +87,7 @@ struct StepArgs {
 };
 int launch_step_boxes(int dtype, const StepArgs &a, const Box *b, int nb, hipStream_t s);
 int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s);
+int launch_step_boundary(int dtype, const StepArgs &a, const Split &sp, hipStream_t s);
 
 struct AdjArgs {
     void *lam_n;

@@ -5,14 +5,14 @@
 // do not depend on which of them computed it:
 //   k_step_boxes   one thread per point over up to six boxes (the boundary
 //                  slabs of the boundary-first schedule); plain global loads.
-//   k_step_zmarch  the inner region: each work-group owns a TW x BY tile of
-//                  (x, y) columns and marches up a chunk of z planes.  Every
-//                  thread keeps its column's T at k-1, k, k+1 (and k+2 in
-//                  flight) in registers, writes plane k to a double-buffered
-//                  LDS tile, and reads its x and y neighbours from there.
-//                  The tile's first and last thread rows only load the
-//                  y-halo rows; two lanes per row load the x-halo points.
-//                  Loads are 16 bytes per lane where the row length allows.
+//   k_step_zmarch  the inner region and the x slabs: each work-group owns a
+//                  TW x TH tile of (x, y) columns and marches up a chunk of z
+//                  planes.  Every thread keeps T at k-1, k, k+1 (and k+2 in
+//                  flight) for its RY rows of VEC points in registers, writes
+//                  plane k to a double-buffered LDS tile, and takes its x and
+//                  y neighbours from there or from its own registers.  Thread
+//                  rows 0 and TY-1 also load the y-halo rows, lanes 0 and
+//                  BX-1 the x-halo points.
 #include <stdlib.h>
 
 #include "host.hpp"
@@ -66,108 +66,160 @@ k_step_boxes(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__ 
 }
 
 // --------------------------------------------------------------- z-march
+// Up to two boxes per launch: work-groups [0, split_block) tile box 0, the
+// rest tile box 1 (the two x slabs of the boundary go in one launch).
+struct ZBox {
+    Box b;
+    int xa;        // first x of the tile grid (b.i0 rounded down to the vector width)
+    int ntx, nty;  // tiles in x and y
+};
 struct ZTile {
-    Box b;        // region to compute
+    ZBox box[2];
+    int64_t split_block;
     int nx, ny;   // array sizes in x and y
-    int xa;       // first x of the tile grid (b.i0 rounded down to the vector width)
-    int ntx, nty; // tiles in x and y
     int zc;       // planes per work-group
     int remap;    // XCD-aware renumbering of work-groups
 };
 
-template <typename S, int VEC, int BX, int BYT>
-__global__ void __launch_bounds__(BX *BYT)
+// BX x TY threads; thread (tx, ty) owns RY consecutive rows of VEC points.
+// Tile: TW = BX*VEC points by TH = TY*RY rows; the LDS plane tile adds one
+// halo row above and below (loaded by thread rows 0 and TY-1) and one halo
+// column left and right (loaded by lanes tx = 0 and BX-1).
+template <typename S, int VEC, int BX, int TY, int RY>
+__global__ void __launch_bounds__(BX *TY)
 k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__ Ci, ZTile z,
               compute_t<S> a, compute_t<S> rx, compute_t<S> ry, compute_t<S> rz, uint32_t key,
               int stochastic)
 {
     using C = compute_t<S>;
     using V = typename VecOf<S, VEC>::type;
-    constexpr int TW = BX * VEC;  // tile width in points
-    constexpr int BY = BYT - 2;   // rows computed per tile
-    constexpr int LW = TW + 2;
-    __shared__ C tile[2][BYT][LW];
+    constexpr int TW = BX * VEC, TH = TY * RY, LH = TH + 2, LW = TW + 2;
+    __shared__ C tile[2][LH][LW];
 
     const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
-    const int64_t g = z.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-    const int bx = (int)(g % z.ntx);
-    const int64_t rest = g / z.ntx;
-    const int by = (int)(rest % z.nty);
-    const int bz = (int)(rest / z.nty);
+    int64_t g = z.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    const int q1 = g >= z.split_block;
+    if (q1) g -= z.split_block;
+    const Box bb = q1 ? z.box[1].b : z.box[0].b;
+    const int xa = q1 ? z.box[1].xa : z.box[0].xa;
+    const int ntx = q1 ? z.box[1].ntx : z.box[0].ntx;
+    const int nty = q1 ? z.box[1].nty : z.box[0].nty;
+    const int bx = (int)(g % ntx);
+    const int64_t rest = g / ntx;
+    const int by = (int)(rest % nty);
+    const int bz = (int)(rest / nty);
 
     const int nx = z.nx, ny = z.ny;
     const int64_t sxy = (int64_t)nx * ny;
-    const int x0 = z.xa + bx * TW;
+    const int x0 = xa + bx * TW;
     const int i = x0 + tx * VEC;
-    const int j = z.b.j0 + by * BY + ty - 1;
-    const int jc = j < 0 ? 0 : (j > ny - 1 ? ny - 1 : j);
     const bool xin = i < nx;
-    const bool crow = ty >= 1 && ty <= BY && j < z.b.j1;
-    const int kb = z.b.k0 + bz * z.zc;
-    const int ke = (kb + z.zc < z.b.k1) ? kb + z.zc : z.b.k1;
-    const int64_t col = (int64_t)jc * nx + i;
-    const bool hl = tx == 0 && x0 >= 1;
-    const bool hr = tx == BX - 1 && x0 + TW < nx;
-    const int64_t colh = (int64_t)jc * nx + (tx == 0 ? x0 - 1 : x0 + TW);
-    const bool own_h = hl || hr;
-    // store mask of this thread's points
-    const bool full = crow && i >= z.b.i0 && i + VEC <= z.b.i1;
+    const int jb = bb.j0 + by * TH;  // first row of the tile
+    const int kb = bb.k0 + bz * z.zc;
+    const int ke = (kb + z.zc < bb.k1) ? kb + z.zc : bb.k1;
+    int64_t col[RY];
+    int jr[RY];
+    bool crow[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        jr[r] = jb + ty * RY + r;
+        const int jc = jr[r] > ny - 1 ? ny - 1 : jr[r];
+        col[r] = (int64_t)jc * nx + i;
+        crow[r] = jr[r] < bb.j1;
+    }
+    // y-halo row of this thread row (thread rows 0 and TY-1 only)
+    const bool hy = ty == 0 || ty == TY - 1;
+    const int jh = (ty == 0) ? jb - 1 : (jb + TH > ny - 1 ? ny - 1 : jb + TH);
+    const int64_t colhy = (int64_t)jh * nx + i;
+    const int hyrow = (ty == 0) ? 0 : LH - 1;
+    // x-halo points of this thread's rows (lanes 0 and BX-1 only)
+    const bool own_h = (tx == 0 && x0 >= 1) || (tx == BX - 1 && x0 + TW < nx);
+    const int xh = (tx == 0) ? x0 - 1 : x0 + TW;
+    const int hcol = (tx == 0) ? 0 : LW - 1;
 
-    auto ldv = [&](const S *A, int k) -> V {
+    auto ldv = [&](const S *A, int k, int64_t c) -> V {
         V v{};
-        if (xin) v = *reinterpret_cast<const V *>(A + (int64_t)k * sxy + col);
+        if (xin) v = *reinterpret_cast<const V *>(A + (int64_t)k * sxy + c);
         return v;
     };
 
-    V zm = ldv(T, kb - 1), zc = ldv(T, kb), zp = ldv(T, kb + 1);
-    V ci = crow ? ldv(Ci, kb) : V{};
-    S h = own_h ? T[(int64_t)kb * sxy + colh] : S(0);
+    // T of planes k-1, k, k+1 per row, Ci of plane k, halo values of plane k
+    V tm[RY], tc[RY], tp[RY], ci[RY];
+    S hx[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        tm[r] = ldv(T, kb - 1, col[r]);
+        tc[r] = ldv(T, kb, col[r]);
+        tp[r] = ldv(T, kb + 1, col[r]);
+        ci[r] = crow[r] ? ldv(Ci, kb, col[r]) : V{};
+        hx[r] = own_h ? T[(int64_t)kb * sxy + col[r] - i + xh] : S(0);
+    }
+    V yh = hy ? ldv(T, kb, colhy) : V{};
 
     for (int k = kb; k < ke; ++k) {
         const int buf = (k - kb) & 1;
         const bool more = k + 1 < ke;
         // loads for the next plane, consumed one iteration later
-        V zn{}, cin{};
-        S hn = S(0);
-        if (more) {
-            zn = ldv(T, k + 2);
-            if (crow) cin = ldv(Ci, k + 1);
-            if (own_h) hn = T[(int64_t)(k + 1) * sxy + colh];
+        V tn[RY], cn[RY], yn{};
+        S hn[RY];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            tn[r] = more ? ldv(T, k + 2, col[r]) : V{};
+            cn[r] = (more && crow[r]) ? ldv(Ci, k + 1, col[r]) : V{};
+            hn[r] = (more && own_h) ? T[(int64_t)(k + 1) * sxy + col[r] - i + xh] : S(0);
         }
+        if (more && hy) yn = ldv(T, k + 1, colhy);
         // plane k into LDS
 #pragma unroll
-        for (int q = 0; q < VEC; ++q) tile[buf][ty][1 + tx * VEC + q] = widen<C>(lane_elem<S, VEC>(zc, q));
-        if (own_h) tile[buf][ty][tx == 0 ? 0 : LW - 1] = widen<C>(h);
+        for (int r = 0; r < RY; ++r) {
+#pragma unroll
+            for (int q = 0; q < VEC; ++q)
+                tile[buf][1 + ty * RY + r][1 + tx * VEC + q] = widen<C>(lane_elem<S, VEC>(tc[r], q));
+            if (own_h) tile[buf][1 + ty * RY + r][hcol] = widen<C>(hx[r]);
+        }
+        if (hy) {
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) tile[buf][hyrow][1 + tx * VEC + q] = widen<C>(lane_elem<S, VEC>(yh, q));
+        }
         __syncthreads();
-        if (crow) {
+        const uint32_t pk = stochastic ? plane_key(key, k) : 0u;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            if (!crow[r]) continue;
+            const int lr = 1 + ty * RY + r;
             V out;
-            uint32_t pk = stochastic ? plane_key(key, k) : 0u;
 #pragma unroll
             for (int q = 0; q < VEC; ++q) {
                 const int lc = 1 + tx * VEC + q;
-                C c = widen<C>(lane_elem<S, VEC>(zc, q));
-                C xm = (q == 0) ? tile[buf][ty][lc - 1] : widen<C>(lane_elem<S, VEC>(zc, q - 1));
-                C xp = (q == VEC - 1) ? tile[buf][ty][lc + 1] : widen<C>(lane_elem<S, VEC>(zc, q + 1));
-                C v = diffuse<C>(c, xm, xp, tile[buf][ty - 1][lc], tile[buf][ty + 1][lc],
-                                 widen<C>(lane_elem<S, VEC>(zm, q)), widen<C>(lane_elem<S, VEC>(zp, q)),
-                                 widen<C>(lane_elem<S, VEC>(ci, q)), a, rx, ry, rz);
-                uint32_t r = stochastic ? point_bits(pk, i + q, j, nx) : 0u;
-                set_elem<S, VEC>(out, q, Store<S>::put(v, r, stochastic));
+                const C c = widen<C>(lane_elem<S, VEC>(tc[r], q));
+                const C xm = (q == 0) ? tile[buf][lr][lc - 1] : widen<C>(lane_elem<S, VEC>(tc[r], q - 1));
+                const C xp = (q == VEC - 1) ? tile[buf][lr][lc + 1] : widen<C>(lane_elem<S, VEC>(tc[r], q + 1));
+                const C ym = (r == 0) ? tile[buf][lr - 1][lc] : widen<C>(lane_elem<S, VEC>(tc[r - 1], q));
+                const C yp = (r == RY - 1) ? tile[buf][lr + 1][lc] : widen<C>(lane_elem<S, VEC>(tc[r + 1], q));
+                const C v = diffuse<C>(c, xm, xp, ym, yp, widen<C>(lane_elem<S, VEC>(tm[r], q)),
+                                       widen<C>(lane_elem<S, VEC>(tp[r], q)), widen<C>(lane_elem<S, VEC>(ci[r], q)),
+                                       a, rx, ry, rz);
+                const uint32_t rb = stochastic ? point_bits(pk, i + q, jr[r], nx) : 0u;
+                set_elem<S, VEC>(out, q, Store<S>::put(v, rb, stochastic));
             }
-            S *dst = T2 + (int64_t)k * sxy + col;
-            if (full) {
+            S *dst = T2 + (int64_t)k * sxy + col[r];
+            if (xin && i >= bb.i0 && i + VEC <= bb.i1) {
                 *reinterpret_cast<V *>(dst) = out;
             } else if (xin) {
 #pragma unroll
                 for (int q = 0; q < VEC; ++q)
-                    if (i + q >= z.b.i0 && i + q < z.b.i1) dst[q] = lane_elem<S, VEC>(out, q);
+                    if (i + q >= bb.i0 && i + q < bb.i1) dst[q] = lane_elem<S, VEC>(out, q);
             }
         }
-        zm = zc;
-        zc = zp;
-        zp = zn;
-        ci = cin;
-        h = hn;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            tm[r] = tc[r];
+            tc[r] = tp[r];
+            tp[r] = tn[r];
+            ci[r] = cn[r];
+            hx[r] = hn[r];
+        }
+        yh = yn;
     }
 }
 
@@ -200,34 +252,40 @@ int launch_step_boxes(int dtype, const StepArgs &a, const Box *b, int nb, hipStr
     return run_boxes<_Float16>(a, b, nb, s);
 }
 
-template <typename S, int VEC, int BX, int BYT>
-static int run_zmarch(const StepArgs &a, const Box &b, hipStream_t s)
+// Tile one or two boxes with TW x (BYT-2) tiles and march zc planes per
+// work-group.  Chunks of 16 planes gave the best HBM throughput on MI355X
+// at 512^3 (many short marches balance the 256 CUs; the two extra planes
+// per chunk are served from cache), and the plain work-group order beat the
+// XCD renumbering there.
+template <typename S, int VEC, int BX, int TY, int RY>
+static int run_zmarch(const StepArgs &a, const Box *b, int nbox, hipStream_t s, int zc_default = 16,
+                      const char *zc_env = "IGG_ZCHUNK")
 {
     using C = compute_t<S>;
-    constexpr int TW = BX * VEC, BY = BYT - 2;
-    ZTile z;
-    z.b = b;
+    constexpr int TW = BX * VEC, BY = TY * RY;
+    ZTile z{};
     z.nx = a.nx;
     z.ny = a.ny;
-    z.xa = (b.i0 / VEC) * VEC;
-    z.ntx = (b.i1 - z.xa + TW - 1) / TW;
-    z.nty = (b.j1 - b.j0 + BY - 1) / BY;
-    int depth = b.k1 - b.k0;
-    int zc = env_int("IGG_ZCHUNK", 0);
-    if (zc <= 0) {
-        // enough work-groups to fill 256 CUs several times over, with long
-        // enough marches that the two extra planes per chunk stay cheap
-        int64_t cols = (int64_t)z.ntx * z.nty;
-        int64_t want = 2048;
-        int64_t chunks = (want + cols - 1) / cols;
-        zc = (int)((depth + chunks - 1) / chunks);
-        if (zc < 16) zc = 16;
-    }
-    if (zc > depth) zc = depth;
+    int zc = env_int(zc_env, zc_default);
+    if (zc < 1) zc = 1;
     z.zc = zc;
-    z.remap = env_int("IGG_XCD_REMAP", 1);
-    int64_t blocks = (int64_t)z.ntx * z.nty * ((depth + zc - 1) / zc);
-    hipLaunchKernelGGL((k_step_zmarch<S, VEC, BX, BYT>), dim3((unsigned)blocks), dim3(BX * BYT), 0, s,
+    z.remap = env_int("IGG_XCD_REMAP", 0);
+    int64_t blocks = 0;
+    z.split_block = INT64_MAX;
+    for (int q = 0; q < nbox; ++q) {
+        ZBox &zb = z.box[q];
+        zb.b = b[q];
+        zb.xa = (b[q].i0 / VEC) * VEC;
+        zb.ntx = (b[q].i1 - zb.xa + TW - 1) / TW;
+        zb.nty = (b[q].j1 - b[q].j0 + BY - 1) / BY;
+        int depth = b[q].k1 - b[q].k0;
+        int64_t nb = (int64_t)zb.ntx * zb.nty * ((depth + zc - 1) / zc);
+        if (q == 1) z.split_block = blocks;
+        blocks += nb;
+    }
+    if (nbox == 1) z.box[1] = z.box[0];
+    if (blocks == 0) return IGG_OK;
+    hipLaunchKernelGGL((k_step_zmarch<S, VEC, BX, TY, RY>), dim3((unsigned)blocks), dim3(BX * TY), 0, s,
                        (S *)a.T2, (const S *)a.T, (const S *)a.Ci, z, (C)a.a, (C)a.rx, (C)a.ry, (C)a.rz,
                        a.key, a.stochastic);
     IGG_HIP(hipGetLastError());
@@ -243,18 +301,57 @@ static bool vec_ok(const StepArgs &a)
     return a.nx % VEC == 0 && aligned(a.T, vb) && aligned(a.T2, vb) && aligned(a.Ci, vb);
 }
 
+// Inner region: tiles whose rows are 512 bytes wide (64 FP64, 128 FP32 or
+// 256 FP16 points, 16- or 8-byte loads per lane), two rows per thread; these
+// shapes gave the highest HBM throughput on MI355X at 512^3.  Rows whose
+// length does not allow vector loads take the one-point-per-lane kernel.
 int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s)
 {
     if (dtype == IGG_F64) {
-        if (vec_ok<double, 2>(a)) return run_zmarch<double, 2, 32, 16>(a, b, s);
-        return run_zmarch<double, 1, 64, 8>(a, b, s);
+        if (vec_ok<double, 2>(a)) return run_zmarch<double, 2, 32, 16, 2>(a, &b, 1, s);
+        return run_zmarch<double, 1, 64, 8, 2>(a, &b, 1, s);
     }
     if (dtype == IGG_F32) {
-        if (vec_ok<float, 4>(a)) return run_zmarch<float, 4, 16, 16>(a, b, s);
-        return run_zmarch<float, 1, 64, 8>(a, b, s);
+        if (vec_ok<float, 2>(a)) return run_zmarch<float, 2, 64, 8, 2>(a, &b, 1, s);
+        return run_zmarch<float, 1, 64, 8, 2>(a, &b, 1, s);
     }
-    if (vec_ok<_Float16, 8>(a)) return run_zmarch<_Float16, 8, 16, 16>(a, b, s);
-    return run_zmarch<_Float16, 1, 64, 8>(a, b, s);
+    if (vec_ok<_Float16, 4>(a)) return run_zmarch<_Float16, 4, 64, 8, 2>(a, &b, 1, s);
+    return run_zmarch<_Float16, 1, 64, 8, 2>(a, &b, 1, s);
+}
+
+// x slabs: narrow 16-point-wide tiles (one 128-byte line of FP64 per row),
+// 32 rows per tile and 8 planes per work-group, so the two slabs still give
+// a few thousand work-groups; the other slabs are whole rows or planes and
+// go through the box kernel.
+static int launch_xslabs(int dtype, const StepArgs &a, const Box *b, int nb, hipStream_t s)
+{
+    const char *ev = "IGG_XSLAB_ZCHUNK";
+    if (dtype == IGG_F64) {
+        if (vec_ok<double, 2>(a)) return run_zmarch<double, 2, 8, 32, 1>(a, b, nb, s, 8, ev);
+        return run_zmarch<double, 1, 16, 16, 1>(a, b, nb, s, 8, ev);
+    }
+    if (dtype == IGG_F32) {
+        if (vec_ok<float, 2>(a)) return run_zmarch<float, 2, 8, 32, 1>(a, b, nb, s, 8, ev);
+        return run_zmarch<float, 1, 16, 16, 1>(a, b, nb, s, 8, ev);
+    }
+    if (vec_ok<_Float16, 2>(a)) return run_zmarch<_Float16, 2, 8, 32, 1>(a, b, nb, s, 8, ev);
+    return run_zmarch<_Float16, 1, 16, 16, 1>(a, b, nb, s, 8, ev);
+}
+
+int launch_step_boundary(int dtype, const StepArgs &a, const Split &sp, hipStream_t s)
+{
+    Box xs[2], other[6];
+    int nxs = 0, nother = 0;
+    for (int q = 0; q < sp.nb; ++q) {
+        if (sp.kind[q] == 0)
+            xs[nxs++] = sp.boundary[q];
+        else
+            other[nother++] = sp.boundary[q];
+    }
+    int rc;
+    if (nother && (rc = launch_step_boxes(dtype, a, other, nother, s))) return rc;
+    if (nxs && (rc = launch_xslabs(dtype, a, xs, nxs, s))) return rc;
+    return IGG_OK;
 }
 
 }  // namespace igg

@@ -47,96 +47,152 @@ def forward(T, Ci, nt, lam, dt, dx, dy, dz, split=(16, 2, 2), work=None, sr_seed
     return a
 
 
-# --------------------------------------------------------------------------- checkpointing
-def schedule_periodic(nt, every):
-    """Snapshot steps of periodic checkpointing: 0, every, 2*every, ..."""
-    return list(range(0, nt, every))
+# --------------------------------------------------------------------------- adjoint sweep
+class Problem:
+    """Constants of one time loop: lam, dt (held fixed), spacings, split."""
+
+    def __init__(self, lam, dt, dx, dy, dz, split=(16, 2, 2)):
+        self.lam, self.dt, self.dx, self.dy, self.dz = lam, dt, dx, dy, dz
+        self.split = split
+
+    def step(self, out, T, Ci, stream=None):
+        igg.diffusion_step(out, T, Ci, self.lam, self.dt, self.dx, self.dy, self.dz, split=self.split,
+                           stream=stream)
+
+    def adjoint(self, lam_n, lam_np1, Tn, Ci, gCi, stream=None):
+        igg.diffusion_step_adjoint(lam_n, lam_np1, Tn, Ci, gCi, self.lam, self.dt, self.dx, self.dy, self.dz,
+                                   split=self.split, stream=stream)
 
 
-def schedule_sqrt(nt):
-    """About sqrt(nt) evenly spaced snapshots."""
-    return schedule_periodic(nt, max(1, int(round(math.sqrt(nt)))))
+class Sweep:
+    """Runs a checkpointing schedule (paper_2211_15716_amd.checkpoint) on the
+    GPU.  Snapshots are device tensors; the current state is either a
+    snapshot (read only) or one of two work buffers, so advancing never
+    overwrites a snapshot.  Counts forward and adjoint steps."""
+
+    def __init__(self, prob, Ci, T0, ops):
+        self.p, self.Ci, self.ops = prob, Ci, ops
+        self.store = {0: T0}
+        self.work = [torch.empty_like(T0), torch.empty_like(T0)]
+        self.cur, self.cur_n = T0, 0
+        self.advances = 0
+        self.adjoints = 0
+        self.peak = 1
+        self.fwd, self.rev = _split_ops(ops)
+
+    def _advance(self, a, b):
+        assert self.cur_n == a, (a, self.cur_n)
+        for _ in range(a, b):
+            dst = self.work[0] if self.cur is not self.work[0] else self.work[1]
+            self.p.step(dst, self.cur, self.Ci)
+            self.cur = dst
+            self.advances += 1
+        self.cur_n = b
+
+    def _do(self, op):
+        kind = op[0]
+        if kind == "restore":
+            self.cur, self.cur_n = self.store[op[1]], op[1]
+        elif kind == "advance":
+            self._advance(op[1], op[2])
+        elif kind == "store":
+            assert self.cur_n == op[1]
+            self.store[op[1]] = self.cur.clone()
+            self.peak = max(self.peak, len(self.store))
+        elif kind == "free":
+            if op[1] != 0:
+                del self.store[op[1]]
+        else:
+            raise ValueError(op)
+
+    def forward(self, nt):
+        """The forward sweep; returns T_nt (a new tensor)."""
+        for op in self.fwd:
+            self._do(op)
+        out = torch.empty_like(self.cur)
+        if nt > 0:
+            self.p.step(out, self.cur, self.Ci)
+            self.advances += 1
+        else:
+            out.copy_(self.cur)
+        return out
+
+    def reverse(self, lam_nt):
+        """The reverse sweep from lam_nt = dLoss/dT_nt (valid halo); returns
+        (dLoss/dT_0, dLoss/dCi) with the Ci gradient on the inner points."""
+        lp = lam_nt
+        ln = torch.empty_like(lp)
+        gCi = torch.zeros_like(lp)
+        for op in self.rev:
+            if op[0] == "adjoint":
+                assert self.cur_n == op[1], (op, self.cur_n)
+                self.p.adjoint(ln, lp, self.cur, self.Ci, gCi)
+                lp, ln = ln, lp
+                self.adjoints += 1
+            else:
+                self._do(op)
+        return lp, gCi
 
 
-def binomial_reps(steps, snaps):
-    """Smallest number r of forward sweeps per step such that binomial
-    checkpointing with `snaps` snapshots covers `steps` steps: the least r with
-    C(snaps + r, snaps) >= steps (Griewank and Walther, ACM TOMS 26, 2000)."""
-    r = 0
-    while math.comb(snaps + r, snaps) < steps:
-        r += 1
-    return r
+def checkpoint_ops(kind, nt, arg=None):
+    """Schedule of paper_2211_15716_amd.checkpoint by name."""
+    from . import checkpoint
+    return checkpoint.make(kind, nt, arg)
 
 
-def binomial_forward_cost(steps, snaps):
-    """Forward steps spent by optimal binomial checkpointing to reverse
-    `steps` steps with `snaps` snapshots (the initial state is held apart):
-    r*steps - C(snaps + r, snaps - 1) + 1 with r from binomial_reps
-    (Griewank, Optim. Methods Softw. 1, 1992), counting the first sweep."""
-    if steps <= 1:
-        return 0
-    r = binomial_reps(steps, snaps)
-    return r * steps - math.comb(snaps + r, snaps - 1) + 1
+def _split_ops(ops):
+    for q, op in enumerate(ops):
+        if op[0] == "adjoint":
+            return ops[:q], ops[q:]
+    return ops, []
 
 
-class _Revolve:
-    """Binomial checkpointing plan (Griewank and Walther's Revolve idea):
-    recursively reverse `steps` steps from a stored state with `snaps` free
-    snapshot slots, advancing to the split point that the binomial
-    coefficients make optimal, storing it, reversing the right part, then the
-    left part with one slot fewer... and one slot returned."""
+def _inner_only(t):
+    out = torch.zeros_like(t)
+    out[1:-1, 1:-1, 1:-1] = t[1:-1, 1:-1, 1:-1]
+    return out
 
-    def __init__(self, steps, snaps):
-        self.steps, self.snaps = steps, snaps
+
+class DiffusionSolve(torch.autograd.Function):
+    """T_nt = nt steps of the Fig. 1 time loop from T0 with heat-capacity
+    inverse Ci; differentiable in T0 and Ci by the hand-written adjoint
+    kernels, with time-loop checkpointing.
+
+    forward(T0, Ci, prob, nt, schedule) -- schedule is ("store_all",),
+    ("periodic", k), ("sqrt",) or ("binomial", slots).  T0 and Ci must carry
+    valid halos.  The gradients returned are zero on halo points: the loss
+    may only depend on the unique (inner) points, and the incoming gradient
+    is restricted to them and then given the periodic halo."""
 
     @staticmethod
-    def split_point(steps, snaps):
-        if snaps <= 0 or steps <= 1:
-            return 0
-        r = binomial_reps(steps, snaps)
-        # largest forward advance for which the remaining parts stay within r sweeps
-        best = max(1, min(steps - 1, math.comb(snaps + r - 1, snaps)))
-        # the right part (steps - adv) must be reversible with snaps-1 slots and r sweeps,
-        # the left part (adv) with snaps slots and r-1 sweeps
-        adv = steps - min(steps - 1, math.comb(snaps - 1 + r, snaps - 1))
-        adv = max(1, min(adv, best))
-        return adv
+    def forward(ctx, T0, Ci, prob, nt, schedule=("store_all",)):
+        from . import checkpoint
+        ops = checkpoint.make(schedule[0], nt, schedule[1] if len(schedule) > 1 else None)
+        sweep = Sweep(prob, Ci, T0.detach(), ops)
+        out = sweep.forward(nt)
+        ctx.sweep = sweep
+        ctx.nt = nt
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        sweep = ctx.sweep
+        lam_nt = _inner_only(g.contiguous())
+        igg.update_halo(lam_nt)
+        gT0, gCi = sweep.reverse(lam_nt)
+        ctx.sweep = None
+        return _inner_only(gT0), _inner_only(gCi), None, None, None
 
 
-def reverse_sweep_plan(nt, snaps):
-    """Operations of binomial checkpointing for nt steps with `snaps` snapshot
-    slots beside the initial state, as a list of ("advance", from, to),
-    ("store", step), ("restore", step), ("adjoint", step), ("free", step).
-    Used by tests to check validity and cost; the autograd driver executes
-    the same plan."""
-    ops = []
-
-    def rev(start, end, slots):
-        # state at `start` is available (stored); reverse steps start..end-1
-        n = end - start
-        if n == 0:
-            return
-        if n == 1:
-            ops.append(("restore", start))
-            ops.append(("adjoint", start))
-            return
-        if slots <= 0:
-            # no free slot: recompute from start for every step
-            for s in range(end - 1, start - 1, -1):
-                ops.append(("restore", start))
-                if s > start:
-                    ops.append(("advance", start, s))
-                ops.append(("adjoint", s))
-            return
-        adv = _Revolve.split_point(n, slots)
-        mid = start + adv
-        ops.append(("restore", start))
-        ops.append(("advance", start, mid))
-        ops.append(("store", mid))
-        rev(mid, end, slots - 1)
-        ops.append(("free", mid))
-        rev(start, mid, slots)
-
-    ops.append(("store", 0))
-    rev(0, nt, snaps)
-    return ops
+def loss_and_grad(T0, Ci, T_obs, prob, nt, schedule=("store_all",)):
+    """0.5*||T_nt - T_obs||^2 over the unique points (FP64 reduction on the
+    GPU) and its gradients (dL/dT0, dL/dCi), by DiffusionSolve."""
+    from . import checkpoint
+    ops = checkpoint.make(schedule[0], nt, schedule[1] if len(schedule) > 1 else None)
+    sweep = Sweep(prob, Ci, T0, ops)
+    Tnt = sweep.forward(nt)
+    L = igg.reduce(igg.RED_HALF_SQDIFF, Tnt, T_obs)
+    lam_nt = _inner_only(Tnt - T_obs)
+    igg.update_halo(lam_nt)
+    gT0, gCi = sweep.reverse(lam_nt)
+    return L, _inner_only(gT0), _inner_only(gCi), sweep

@@ -81,7 +81,7 @@ def load():
     lib.igg_reduce.argtypes = [ctypes.c_int, _PF, _PF, ctypes.POINTER(d), vp]
     lib.igg_plan_split.argtypes = [_PI, _PI, (ctypes.c_int * 6) * 7, _PI]
     lib.igg_timing_enable.argtypes = [ctypes.c_int]
-    lib.igg_timing_read.argtypes = [ctypes.POINTER(d), i64p, i64p]
+    lib.igg_timing_read.argtypes = [ctypes.POINTER(d), i64p, i64p, ctypes.POINTER(d)]
     lib.igg_last_error.restype = ctypes.c_char_p
     lib.igg_version.restype = ctypes.c_char_p
     _lib_handle = lib
@@ -232,11 +232,14 @@ def timing_enable(on=True):
 
 
 def timing_read():
+    """(inner ms, inner launches, inner points, boundary ms) since the last read."""
     ms = ctypes.c_double()
+    bms = ctypes.c_double()
     launches = ctypes.c_int64()
     points = ctypes.c_int64()
-    _check(load().igg_timing_read(ctypes.byref(ms), ctypes.byref(launches), ctypes.byref(points)))
-    return ms.value, launches.value, points.value
+    _check(load().igg_timing_read(ctypes.byref(ms), ctypes.byref(launches), ctypes.byref(points),
+                                  ctypes.byref(bms)))
+    return ms.value, launches.value, points.value, bms.value
 
 
 def version():

@@ -1,0 +1,218 @@
+"""Adjoint sweep on the GPU: checkpointed equals store-all bit for bit,
+parity with the oracle's gradient, the autograd path, the dot-product test,
+central finite differences, and the 256^3 inverse-problem configuration."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2211_15716_amd import diffusion, igg, synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+from gpu_common import dev, grid, host, inner, say  # noqa: E402
+
+
+def _fields(n, seed):
+    nx, ny, nz = n
+    T0, Ci, Tobs = synth.uniform_fields(nx, ny, nz, seed=seed, lo=0.3, hi=0.9, n=3)
+    for a in (T0, Ci, Tobs):
+        oracle.halo(a)
+    return T0, Ci, Tobs
+
+
+@pytest.mark.parametrize("split", [(16, 2, 2), None])
+def test_checkpointed_equals_store_all_and_oracle(split):
+    say("checkpointed adjoint", split)
+    n = (40, 34, 30)
+    nt = 17
+    T0, Ci, Tobs = _fields(n, 51)
+    dx, dy, dz = 1 / 39, 1 / 33, 1 / 29
+    dt = oracle.time_step(dx, dy, dz, 1.0, oracle.max_all(Ci))
+    L_ref, gT_ref, gC_ref = oracle.gradient(T0, Ci, Tobs, nt, 1.0, dt, dx, dy, dz)
+    with grid(n):
+        prob = diffusion.Problem(1.0, dt, dx, dy, dz, split=split)
+        T, C, O = dev(T0), dev(Ci), dev(Tobs)
+        res = {}
+        for sched in [("store_all",), ("periodic", 4), ("sqrt",), ("binomial", 3), ("binomial", 1)]:
+            L, gT, gC, sw = diffusion.loss_and_grad(T, C, O, prob, nt, sched)
+            res[sched] = (L, host(gT), host(gC), sw.advances)
+        L0, gT0, gC0, adv0 = res[("store_all",)]
+        assert adv0 == nt
+        for sched, (L, gT, gC, adv) in res.items():
+            assert L == L0 and np.array_equal(gT, gT0) and np.array_equal(gC, gC0), sched
+    assert abs(L0 - L_ref) <= 1e-12 * L_ref
+    assert np.max(np.abs(inner(gT0) - inner(gT_ref))) <= 1e-12 * np.max(np.abs(inner(gT_ref)))
+    assert np.max(np.abs(inner(gC0) - inner(gC_ref))) <= 1e-12 * np.max(np.abs(inner(gC_ref)))
+
+
+@pytest.mark.parametrize("split", [None, (16, 2, 2)])
+def test_adjoint_multi_tile_matches_oracle(split):
+    """A grid spanning several x and y tiles and z chunks of the adjoint
+    kernel, with ragged tails."""
+    say("adjoint multi-tile", split)
+    n = (150, 60, 45)
+    nt = 6
+    T0, Ci, Tobs = _fields(n, 56)
+    dx, dy, dz = 1 / 149, 1 / 59, 1 / 44
+    dt = oracle.time_step(dx, dy, dz, 1.0, oracle.max_all(Ci))
+    L_ref, gT_ref, gC_ref = oracle.gradient(T0, Ci, Tobs, nt, 1.0, dt, dx, dy, dz)
+    with grid(n):
+        prob = diffusion.Problem(1.0, dt, dx, dy, dz, split=split)
+        L, gT, gC, _ = diffusion.loss_and_grad(dev(T0), dev(Ci), dev(Tobs), prob, nt)
+        gT, gC = host(gT), host(gC)
+    assert abs(L - L_ref) <= 1e-12 * L_ref
+    assert np.max(np.abs(inner(gT) - inner(gT_ref))) <= 1e-12 * np.max(np.abs(inner(gT_ref)))
+    assert np.max(np.abs(inner(gC) - inner(gC_ref))) <= 1e-12 * np.max(np.abs(inner(gC_ref)))
+
+
+def test_autograd_function_matches_sweep():
+    say("autograd")
+    n = (36, 30, 28)
+    nt = 9
+    T0, Ci, Tobs = _fields(n, 52)
+    dx = 1 / 35
+    dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
+    with grid(n):
+        prob = diffusion.Problem(1.0, dt, dx, dx, dx)
+        T, C, O = dev(T0), dev(Ci), dev(Tobs)
+        L, gT, gC, _ = diffusion.loss_and_grad(T, C, O, prob, nt, ("binomial", 4))
+        Ta, Ca = T.clone().requires_grad_(True), C.clone().requires_grad_(True)
+        out = diffusion.DiffusionSolve.apply(Ta, Ca, prob, nt, ("periodic", 3))
+        r = (out - O)[1:-1, 1:-1, 1:-1]
+        loss = 0.5 * (r * r).sum()
+        loss.backward()
+        assert abs(loss.item() - L) <= 1e-13 * L
+        assert torch.equal(Ta.grad, gT) and torch.equal(Ca.grad, gC)
+
+
+def test_dot_product_on_gpu():
+    """<J d, y> = <d, J^T y> for the map T0 -> T_nt (FP64 reductions)."""
+    say("dot product")
+    n = (48, 40, 36)
+    nt = 12
+    d0, Ci, y = _fields(n, 53)
+    dx = 1 / 47
+    dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
+    with grid(n):
+        prob = diffusion.Problem(1.0, dt, dx, dx, dx)
+        d, C, Y = dev(d0), dev(Ci), dev(y)
+        Jd = diffusion.forward(d.clone(), C, nt, 1.0, dt, dx, dx, dx)
+        lam = torch.zeros_like(Y)
+        lam[1:-1, 1:-1, 1:-1] = Y[1:-1, 1:-1, 1:-1]
+        igg.update_halo(lam)
+        sw = diffusion.Sweep(prob, C, d, diffusion.checkpoint_ops("store_all", nt))
+        sw.forward(nt)
+        JTy, _ = sw.reverse(lam)
+        lhs = igg.reduce(igg.RED_DOT, Jd, Y)
+        rhs = igg.reduce(igg.RED_DOT, d, JTy)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def _central(prob, T, C, O, nt, which, vox, h):
+    """(L(x + h e) - L(x - h e)) / 2h along one unique voxel, the loss
+    difference formed as a dot product of the pointwise state differences
+    (so the unchanged points cancel exactly)."""
+    k, j, i = vox
+    outs = []
+    for sgn in (+1, -1):
+        Cp, Tp = C.clone(), T.clone()
+        if which == "Ci":
+            Cp[k, j, i] += sgn * h
+            igg.update_halo(Cp)
+        else:
+            Tp[k, j, i] += sgn * h
+            igg.update_halo(Tp)
+        outs.append(diffusion.forward(Tp, Cp, nt, prob.lam, prob.dt, prob.dx, prob.dy, prob.dz,
+                                      split=prob.split))
+    diff = outs[0] - outs[1]
+    mid = 0.5 * (outs[0] + outs[1]) - O
+    return igg.reduce(igg.RED_DOT, diff, mid) / (2 * h)
+
+
+def _fd_check(prob, T, C, O, nt, gC, gT, voxels, hrel=1e-2, hT=1e-3):
+    """Finite-difference check at the given inner voxels.  L is quadratic in
+    T0, so its central difference is exact up to rounding; in Ci it is a
+    polynomial of degree nt, so the central difference is Richardson
+    extrapolated from steps h and h/2, cancelling the h^2 error term.  The
+    Ci step is 1e-2*Ci: the loss difference of two FP64 runs carries
+    rounding noise near 1e-17 absolute, and most voxels' gradients are small,
+    so a smaller step would measure that noise rather than the gradient.
+    Relative error where |g| >= 1e-3 max|g|, else absolute over max|g|."""
+    gmax_c = torch.max(torch.abs(gC)).item()
+    gmax_t = torch.max(torch.abs(gT)).item()
+    worst = 0.0
+    for (k, j, i) in voxels:
+        for which in ("Ci", "T0"):
+            if which == "Ci":
+                h = hrel * C[k, j, i].item()
+                f1 = _central(prob, T, C, O, nt, which, (k, j, i), h)
+                f2 = _central(prob, T, C, O, nt, which, (k, j, i), h / 2)
+                fd = (4.0 * f2 - f1) / 3.0
+            else:
+                fd = _central(prob, T, C, O, nt, which, (k, j, i), hT)
+            g = (gC if which == "Ci" else gT)[k, j, i].item()
+            gmax = gmax_c if which == "Ci" else gmax_t
+            if abs(g) >= 1e-3 * gmax:
+                err = abs(fd - g) / abs(g)
+            else:
+                err = abs(fd - g) / gmax
+            worst = max(worst, err)
+    return worst
+
+
+def test_gradient_matches_central_differences_small():
+    say("FD small")
+    n = (30, 26, 22)
+    nt = 10
+    T0, Ci, Tobs = _fields(n, 54)
+    dx = 1 / 29
+    dt = oracle.time_step(dx, dx, dx, 1.0, 1.0)
+    rng = np.random.default_rng(5)
+    vox = [(int(rng.integers(1, 21)), int(rng.integers(1, 25)), int(rng.integers(1, 29))) for _ in range(6)]
+    with grid(n):
+        prob = diffusion.Problem(1.0, dt, dx, dx, dx)
+        T, C, O = dev(T0), dev(Ci), dev(Tobs)
+        _, gT, gC, _ = diffusion.loss_and_grad(T, C, O, prob, nt, ("periodic", 4))
+        worst = _fd_check(prob, T, C, O, nt, gC, gT, vox)
+    assert worst <= 1e-6, worst
+
+
+def test_inverse_problem_256_fd_20_voxels():
+    """256^3 FP64, nt=200, snapshots every 16: T_obs from Ci_true (sine),
+    guess Ci = 0.5, dt fixed from max(Ci_true); dL/dCi and dL/dT0 checked
+    against central differences on 20 random unique voxels."""
+    say("inverse 256^3 nt=200")
+    w = synth.workload("c4_256_inverse", seed=0)
+    n = (w["nx"], w["ny"], w["nz"])
+    nt = w["nt"]
+    with grid(n):
+        T, Ctrue = diffusion.prepare_fields(w["T0"], w["Ci"])
+        dt = igg.diffusion_dt(Ctrue, w["lam"], w["dx"], w["dy"], w["dz"])
+        prob = diffusion.Problem(w["lam"], dt, w["dx"], w["dy"], w["dz"])
+        O = diffusion.forward(T.clone(), Ctrue, nt, prob.lam, dt, prob.dx, prob.dy, prob.dz)
+        C = torch.full_like(T, 0.5)
+        L, gT, gC, sw = diffusion.loss_and_grad(T, C, O, prob, nt, ("periodic", 16))
+        assert sw.adjoints == nt and L > 0
+        rng = np.random.default_rng(0)
+        vox = [tuple(int(v) for v in rng.integers(1, 255, size=3)) for _ in range(20)]
+        worst = _fd_check(prob, T, C, O, nt, gC, gT, vox)
+    assert worst <= 1e-6, worst
+
+
+def test_fp32_adjoint_close_to_fp64():
+    say("fp32 adjoint")
+    n = (40, 36, 32)
+    nt = 10
+    T0, Ci, Tobs = _fields(n, 55)
+    dx = 1 / 39
+    dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
+    with grid(n):
+        prob = diffusion.Problem(1.0, dt, dx, dx, dx)
+        r64 = diffusion.loss_and_grad(dev(T0), dev(Ci), dev(Tobs), prob, nt)
+        r32 = diffusion.loss_and_grad(dev(T0, torch.float32), dev(Ci, torch.float32), dev(Tobs, torch.float32),
+                                      prob, nt)
+        for a, b in ((r64[1], r32[1]), (r64[2], r32[2])):
+            err = torch.max(torch.abs(a - b.double())).item() / torch.max(torch.abs(a)).item()
+            assert err <= 1e-5, err
