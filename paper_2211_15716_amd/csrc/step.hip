@@ -142,6 +142,13 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
         if (xin) v = *reinterpret_cast<const V *>(A + (int64_t)k * sxy + c);
         return v;
     };
+    // Ci and T2 are touched once per step: non-temporal loads and stores keep
+    // them from displacing the T lines that neighbouring tiles reuse
+    auto ldv_nt = [&](const S *A, int k, int64_t c) -> V {
+        V v{};
+        if (xin) v = __builtin_nontemporal_load(reinterpret_cast<const V *>(A + (int64_t)k * sxy + c));
+        return v;
+    };
 
     // T of planes k-1, k, k+1 per row, Ci of plane k, halo values of plane k
     V tm[RY], tc[RY], tp[RY], ci[RY];
@@ -151,7 +158,7 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
         tm[r] = ldv(T, kb - 1, col[r]);
         tc[r] = ldv(T, kb, col[r]);
         tp[r] = ldv(T, kb + 1, col[r]);
-        ci[r] = crow[r] ? ldv(Ci, kb, col[r]) : V{};
+        ci[r] = crow[r] ? ldv_nt(Ci, kb, col[r]) : V{};
         hx[r] = own_h ? T[(int64_t)kb * sxy + col[r] - i + xh] : S(0);
     }
     V yh = hy ? ldv(T, kb, colhy) : V{};
@@ -165,7 +172,7 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             tn[r] = more ? ldv(T, k + 2, col[r]) : V{};
-            cn[r] = (more && crow[r]) ? ldv(Ci, k + 1, col[r]) : V{};
+            cn[r] = (more && crow[r]) ? ldv_nt(Ci, k + 1, col[r]) : V{};
             hn[r] = (more && own_h) ? T[(int64_t)(k + 1) * sxy + col[r] - i + xh] : S(0);
         }
         if (more && hy) yn = ldv(T, k + 1, colhy);
@@ -204,7 +211,7 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
             }
             S *dst = T2 + (int64_t)k * sxy + col[r];
             if (xin && i >= bb.i0 && i + VEC <= bb.i1) {
-                *reinterpret_cast<V *>(dst) = out;
+                __builtin_nontemporal_store(out, reinterpret_cast<V *>(dst));
             } else if (xin) {
 #pragma unroll
                 for (int q = 0; q < VEC; ++q)
