@@ -7,9 +7,9 @@
 //                                               six neighbours)
 //   gCi  += a*lp.*(L T_n)
 // on the inner points.  k_adj_boxes is the one-thread-per-point form used
-// for the boundary slabs; k_adj_zmarch marches z like the forward kernel,
-// keeping lp, Ci and T_n of planes k-1, k, k+1 in registers and staging mu
-// and T_n of plane k in LDS for the x and y neighbours.
+// for the boundary slabs; k_adj_zmarch marches z with the forward kernel's
+// tiling, keeping lp, mu and T_n of planes k-1, k, k+1 in registers and
+// staging mu and T_n of plane k in LDS for the x and y neighbours.
 #include <stdlib.h>
 
 #include "host.hpp"
@@ -54,91 +54,210 @@ struct AdjTile {
     int remap;
 };
 
-// BX x BYT threads, one point per thread; rows 0 and BYT-1 load y-halos.
-template <typename C, int BX, int BYT>
-__global__ void __launch_bounds__(BX *BYT)
+template <typename C, int VEC> struct AVec {
+    typedef C type __attribute__((ext_vector_type(VEC)));
+};
+template <typename C> struct AVec<C, 1> {
+    typedef C type;
+};
+template <typename C, int VEC>
+__device__ __forceinline__ C el(const typename AVec<C, VEC>::type &v, int q)
+{
+    if constexpr (VEC == 1)
+        return v;
+    else
+        return v[q];
+}
+template <typename C, int VEC>
+__device__ __forceinline__ void set_el(typename AVec<C, VEC>::type &v, int q, C x)
+{
+    if constexpr (VEC == 1)
+        v = x;
+    else
+        v[q] = x;
+}
+
+// BX x TY threads, RY rows of VEC points per thread (the forward kernel's
+// tiling).  mu = Ci .* lp and T_n of plane k are staged in two
+// double-buffered LDS tiles; lp, mu and T_n of planes k-1..k+1 (k+2 in
+// flight) sit in registers.  gCi is read and written once per point and
+// lam_n written once: non-temporal.
+template <typename C, int VEC, int BX, int TY, int RY>
+__global__ void __launch_bounds__(BX *TY)
 k_adj_zmarch(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restrict__ Tn,
              const C *__restrict__ Ci, C *__restrict__ gCi, AdjTile z, C a, C rx, C ry, C rz)
 {
-    constexpr int BY = BYT - 2, LW = BX + 2;
-    __shared__ C smu[2][BYT][LW];
-    __shared__ C sT[2][BYT][LW];
+    using V = typename AVec<C, VEC>::type;
+    constexpr int TW = BX * VEC, TH = TY * RY, LH = TH + 2, LW = TW + 2;
+    __shared__ C smu[2][LH][LW];
+    __shared__ C sT[2][LH][LW];
     const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
-    const int64_t g = z.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    int64_t g = blockIdx.x;
+    if (z.remap == 2) {  // x-rows of tiles dealt to the XCDs in turn
+        const int64_t ntx0 = z.ntx, P = gridDim.x / ntx0, P8 = P / 8 * 8;
+        if (g < ntx0 * P8) {
+            const int64_t x = g % 8, slot = g / 8;
+            g = slot % ntx0 + ntx0 * (x + 8 * (slot / ntx0));
+        }
+    }
     const int bx = (int)(g % z.ntx);
     const int64_t rest = g / z.ntx;
     const int by = (int)(rest % z.nty);
     const int bz = (int)(rest / z.nty);
     const int nx = z.nx, ny = z.ny;
     const int64_t sxy = (int64_t)nx * ny;
-    const int x0 = z.xa + bx * BX;
-    const int i = x0 + tx;
-    const int j = z.b.j0 + by * BY + ty - 1;
-    const int jc = j < 0 ? 0 : (j > ny - 1 ? ny - 1 : j);
+    const int x0 = z.xa + bx * TW;
+    const int i = x0 + tx * VEC;
     const bool xin = i < nx;
-    const bool crow = ty >= 1 && ty <= BY && j < z.b.j1 && i >= z.b.i0 && i < z.b.i1;
+    const int jb = z.b.j0 + by * TH;
     const int kb = z.b.k0 + bz * z.zc;
     const int ke = (kb + z.zc < z.b.k1) ? kb + z.zc : z.b.k1;
-    const int64_t col = (int64_t)jc * nx + i;
-    const bool hl = tx == 0 && x0 >= 1;
-    const bool hr = tx == BX - 1 && x0 + BX < nx;
-    const bool own_h = hl || hr;
-    const int64_t colh = (int64_t)jc * nx + (tx == 0 ? x0 - 1 : x0 + BX);
+    int64_t col[RY];
+    bool crow[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        const int j = jb + ty * RY + r;
+        col[r] = (int64_t)(j > ny - 1 ? ny - 1 : j) * nx + i;
+        crow[r] = j < z.b.j1;
+    }
+    const bool hy = ty == 0 || ty == TY - 1;
+    const int jh = (ty == 0) ? jb - 1 : (jb + TH > ny - 1 ? ny - 1 : jb + TH);
+    const int64_t colhy = (int64_t)jh * nx + i;
+    const int hyrow = (ty == 0) ? 0 : LH - 1;
+    const bool own_h = (tx == 0 && x0 >= 1) || (tx == BX - 1 && x0 + TW < nx);
+    const int xh = (tx == 0) ? x0 - 1 : x0 + TW;
+    const int hcol = (tx == 0) ? 0 : LW - 1;
 
-    auto ld = [&](const C *A, int k, int64_t c, bool ok) -> C { return ok ? A[(int64_t)k * sxy + c] : C(0); };
+    auto ld = [&](const C *A, int k, int64_t c) -> V {
+        V v{};
+        if (xin) v = *reinterpret_cast<const V *>(A + (int64_t)k * sxy + c);
+        return v;
+    };
+    auto ld_nt = [&](const C *A, int k, int64_t c) -> V {
+        V v{};
+        if (xin) v = __builtin_nontemporal_load(reinterpret_cast<const V *>(A + (int64_t)k * sxy + c));
+        return v;
+    };
+    auto mul = [](V x, V y) -> V {
+        V out;
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) set_el<C, VEC>(out, q, el<C, VEC>(x, q) * el<C, VEC>(y, q));
+        return out;
+    };
 
-    // mu and T of planes k-1, k, k+1 for this column
-    C mm = ld(Ci, kb - 1, col, xin) * ld(lp, kb - 1, col, xin);
-    C lc = ld(lp, kb, col, xin);
-    C mc = ld(Ci, kb, col, xin) * lc;
-    C lpn = ld(lp, kb + 1, col, xin);
-    C mp = ld(Ci, kb + 1, col, xin) * lpn;
-    C tm = ld(Tn, kb - 1, col, xin), tc = ld(Tn, kb, col, xin), tp = ld(Tn, kb + 1, col, xin);
-    C hmu = own_h ? ld(Ci, kb, colh, true) * ld(lp, kb, colh, true) : C(0);
-    C hT = ld(Tn, kb, colh, own_h);
+    V mm[RY], mc[RY], mp[RY], tm[RY], tc[RY], tp[RY], lc[RY], lq[RY], gc[RY];
+    C hmu[RY], hT[RY];
+#pragma unroll
+    for (int r = 0; r < RY; ++r) {
+        mm[r] = mul(ld(Ci, kb - 1, col[r]), ld(lp, kb - 1, col[r]));
+        lc[r] = ld(lp, kb, col[r]);
+        mc[r] = mul(ld(Ci, kb, col[r]), lc[r]);
+        lq[r] = ld(lp, kb + 1, col[r]);
+        mp[r] = mul(ld(Ci, kb + 1, col[r]), lq[r]);
+        tm[r] = ld(Tn, kb - 1, col[r]);
+        tc[r] = ld(Tn, kb, col[r]);
+        tp[r] = ld(Tn, kb + 1, col[r]);
+        gc[r] = crow[r] ? ld_nt(gCi, kb, col[r]) : V{};
+        const int64_t ph = (int64_t)kb * sxy + col[r] - i + xh;
+        hmu[r] = own_h ? Ci[ph] * lp[ph] : C(0);
+        hT[r] = own_h ? Tn[ph] : C(0);
+    }
+    V ymu = hy ? mul(ld(Ci, kb, colhy), ld(lp, kb, colhy)) : V{};
+    V yT = hy ? ld(Tn, kb, colhy) : V{};
 
     for (int k = kb; k < ke; ++k) {
         const int buf = (k - kb) & 1;
         const bool more = k + 1 < ke;
-        C ln2 = 0, mn = 0, tn = 0, hmu_n = 0, hT_n = 0;
-        if (more) {
-            ln2 = ld(lp, k + 2, col, xin);
-            mn = ld(Ci, k + 2, col, xin) * ln2;
-            tn = ld(Tn, k + 2, col, xin);
+        V mn[RY], tn[RY], ln2[RY], gn[RY], ymu_n{}, yT_n{};
+        C hmu_n[RY], hT_n[RY];
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            ln2[r] = more ? ld(lp, k + 2, col[r]) : V{};
+            mn[r] = more ? mul(ld(Ci, k + 2, col[r]), ln2[r]) : V{};
+            tn[r] = more ? ld(Tn, k + 2, col[r]) : V{};
+            gn[r] = (more && crow[r]) ? ld_nt(gCi, k + 1, col[r]) : V{};
+            const int64_t ph = (int64_t)(k + 1) * sxy + col[r] - i + xh;
+            hmu_n[r] = (more && own_h) ? Ci[ph] * lp[ph] : C(0);
+            hT_n[r] = (more && own_h) ? Tn[ph] : C(0);
+        }
+        if (more && hy) {
+            ymu_n = mul(ld(Ci, k + 1, colhy), ld(lp, k + 1, colhy));
+            yT_n = ld(Tn, k + 1, colhy);
+        }
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const int lr = 1 + ty * RY + r;
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) {
+                smu[buf][lr][1 + tx * VEC + q] = el<C, VEC>(mc[r], q);
+                sT[buf][lr][1 + tx * VEC + q] = el<C, VEC>(tc[r], q);
+            }
             if (own_h) {
-                hmu_n = ld(Ci, k + 1, colh, true) * ld(lp, k + 1, colh, true);
-                hT_n = ld(Tn, k + 1, colh, true);
+                smu[buf][lr][hcol] = hmu[r];
+                sT[buf][lr][hcol] = hT[r];
             }
         }
-        smu[buf][ty][1 + tx] = mc;
-        sT[buf][ty][1 + tx] = tc;
-        if (own_h) {
-            smu[buf][ty][tx == 0 ? 0 : LW - 1] = hmu;
-            sT[buf][ty][tx == 0 ? 0 : LW - 1] = hT;
+        if (hy) {
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) {
+                smu[buf][hyrow][1 + tx * VEC + q] = el<C, VEC>(ymu, q);
+                sT[buf][hyrow][1 + tx * VEC + q] = el<C, VEC>(yT, q);
+            }
         }
         __syncthreads();
-        if (crow) {
-            const int c = 1 + tx;
-            C lapmu = laplace<C>(mc, smu[buf][ty][c - 1], smu[buf][ty][c + 1], smu[buf][ty - 1][c],
-                                 smu[buf][ty + 1][c], mm, mp, rx, ry, rz);
-            C lapT = laplace<C>(tc, sT[buf][ty][c - 1], sT[buf][ty][c + 1], sT[buf][ty - 1][c],
-                                sT[buf][ty + 1][c], tm, tp, rx, ry, rz);
-            const int64_t p = (int64_t)k * sxy + col;
-            C ln, gg = gCi[p];
-            adjoint_point<C>(lc, lapmu, lapT, a, ln, gg);
-            lam_n[p] = ln;
-            gCi[p] = gg;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            if (!crow[r]) continue;
+            const int lr = 1 + ty * RY + r;
+            V lo, go;
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) {
+                const int lc_ = 1 + tx * VEC + q;
+                const C m0 = el<C, VEC>(mc[r], q), t0 = el<C, VEC>(tc[r], q);
+                const C mxm = (q == 0) ? smu[buf][lr][lc_ - 1] : el<C, VEC>(mc[r], q - 1);
+                const C mxp = (q == VEC - 1) ? smu[buf][lr][lc_ + 1] : el<C, VEC>(mc[r], q + 1);
+                const C mym = (r == 0) ? smu[buf][lr - 1][lc_] : el<C, VEC>(mc[r - 1], q);
+                const C myp = (r == RY - 1) ? smu[buf][lr + 1][lc_] : el<C, VEC>(mc[r + 1], q);
+                const C txm = (q == 0) ? sT[buf][lr][lc_ - 1] : el<C, VEC>(tc[r], q - 1);
+                const C txp = (q == VEC - 1) ? sT[buf][lr][lc_ + 1] : el<C, VEC>(tc[r], q + 1);
+                const C tym = (r == 0) ? sT[buf][lr - 1][lc_] : el<C, VEC>(tc[r - 1], q);
+                const C typ = (r == RY - 1) ? sT[buf][lr + 1][lc_] : el<C, VEC>(tc[r + 1], q);
+                const C lapmu = laplace<C>(m0, mxm, mxp, mym, myp, el<C, VEC>(mm[r], q), el<C, VEC>(mp[r], q), rx, ry, rz);
+                const C lapT = laplace<C>(t0, txm, txp, tym, typ, el<C, VEC>(tm[r], q), el<C, VEC>(tp[r], q), rx, ry, rz);
+                C ln, gg = el<C, VEC>(gc[r], q);
+                adjoint_point<C>(el<C, VEC>(lc[r], q), lapmu, lapT, a, ln, gg);
+                set_el<C, VEC>(lo, q, ln);
+                set_el<C, VEC>(go, q, gg);
+            }
+            const int64_t p = (int64_t)k * sxy + col[r];
+            if (xin && i >= z.b.i0 && i + VEC <= z.b.i1) {
+                __builtin_nontemporal_store(lo, reinterpret_cast<V *>(lam_n + p));
+                __builtin_nontemporal_store(go, reinterpret_cast<V *>(gCi + p));
+            } else if (xin) {
+#pragma unroll
+                for (int q = 0; q < VEC; ++q)
+                    if (i + q >= z.b.i0 && i + q < z.b.i1) {
+                        lam_n[p + q] = el<C, VEC>(lo, q);
+                        gCi[p + q] = el<C, VEC>(go, q);
+                    }
+            }
         }
-        mm = mc;
-        mc = mp;
-        mp = mn;
-        lc = lpn;
-        lpn = ln2;
-        tm = tc;
-        tc = tp;
-        tp = tn;
-        hmu = hmu_n;
-        hT = hT_n;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            mm[r] = mc[r];
+            mc[r] = mp[r];
+            mp[r] = mn[r];
+            lc[r] = lq[r];
+            lq[r] = ln2[r];
+            tm[r] = tc[r];
+            tc[r] = tp[r];
+            tp[r] = tn[r];
+            gc[r] = gn[r];
+            hmu[r] = hmu_n[r];
+            hT[r] = hT_n[r];
+        }
+        ymu = ymu_n;
+        yT = yT_n;
     }
 }
 
@@ -166,39 +285,49 @@ int launch_adjoint_boxes(int dtype, const AdjArgs &a, const Box *b, int nb, hipS
     return dtype == IGG_F64 ? run_boxes<double>(a, b, nb, s) : run_boxes<float>(a, b, nb, s);
 }
 
-template <typename C, int BX, int BYT>
+template <typename C, int VEC, int BX, int TY, int RY>
 static int run_zmarch(const AdjArgs &a, const Box &b, hipStream_t s)
 {
-    constexpr int BY = BYT - 2;
+    constexpr int TW = BX * VEC, TH = TY * RY;
     AdjTile z;
     z.b = b;
     z.nx = a.nx;
     z.ny = a.ny;
-    z.xa = b.i0;
-    z.ntx = (b.i1 - b.i0 + BX - 1) / BX;
-    z.nty = (b.j1 - b.j0 + BY - 1) / BY;
+    z.xa = (b.i0 / VEC) * VEC;
+    z.ntx = (b.i1 - z.xa + TW - 1) / TW;
+    z.nty = (b.j1 - b.j0 + TH - 1) / TH;
     int depth = b.k1 - b.k0;
-    int zc = env_int("IGG_ADJ_ZCHUNK", 0);
-    if (zc <= 0) {
-        int64_t cols = (int64_t)z.ntx * z.nty;
-        int64_t chunks = (2048 + cols - 1) / cols;
-        zc = (int)((depth + chunks - 1) / chunks);
-        if (zc < 16) zc = 16;
-    }
-    if (zc > depth) zc = depth;
+    int zc = env_int("IGG_ADJ_ZCHUNK", 16);
+    if (zc < 1) zc = 1;
     z.zc = zc;
-    z.remap = env_int("IGG_XCD_REMAP", 1);
+    z.remap = env_int("IGG_ADJ_REMAP", 2);
     int64_t blocks = (int64_t)z.ntx * z.nty * ((depth + zc - 1) / zc);
-    hipLaunchKernelGGL((k_adj_zmarch<C, BX, BYT>), dim3((unsigned)blocks), dim3(BX * BYT), 0, s,
+    if (blocks == 0) return IGG_OK;
+    hipLaunchKernelGGL((k_adj_zmarch<C, VEC, BX, TY, RY>), dim3((unsigned)blocks), dim3(BX * TY), 0, s,
                        (C *)a.lam_n, (const C *)a.lp, (const C *)a.Tn, (const C *)a.Ci, (C *)a.gCi, z,
                        (C)a.a, (C)a.rx, (C)a.ry, (C)a.rz);
     IGG_HIP(hipGetLastError());
     return IGG_OK;
 }
 
+static bool aligned(const void *p, int bytes) { return ((uintptr_t)p % (uintptr_t)bytes) == 0; }
+
+template <typename C>
+static bool vec2_ok(const AdjArgs &a)
+{
+    const int vb = 2 * (int)sizeof(C);
+    return a.nx % 2 == 0 && aligned(a.lam_n, vb) && aligned(a.lp, vb) && aligned(a.Tn, vb) &&
+           aligned(a.Ci, vb) && aligned(a.gCi, vb);
+}
+
+// 512-byte tile rows (64 FP64 or 128 FP32 points), one row per thread (the
+// two staged fields need many registers); one point per
+// lane where the row length does not allow 16-byte loads.
 int launch_adjoint_inner(int dtype, const AdjArgs &a, const Box &b, hipStream_t s)
 {
-    return dtype == IGG_F64 ? run_zmarch<double, 64, 8>(a, b, s) : run_zmarch<float, 64, 8>(a, b, s);
+    if (dtype == IGG_F64)
+        return vec2_ok<double>(a) ? run_zmarch<double, 2, 32, 16, 1>(a, b, s) : run_zmarch<double, 1, 64, 8, 2>(a, b, s);
+    return vec2_ok<float>(a) ? run_zmarch<float, 2, 64, 8, 1>(a, b, s) : run_zmarch<float, 1, 64, 8, 2>(a, b, s);
 }
 
 }  // namespace igg

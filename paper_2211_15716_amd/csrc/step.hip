@@ -79,13 +79,19 @@ struct ZTile {
     int nx, ny;   // array sizes in x and y
     int zc;       // planes per work-group
     int remap;    // XCD-aware renumbering of work-groups
+    // wrapped x-slab tiles (WRAP): virtual row j holds the last w2 points of
+    // row j-1 and the first w2 points of row j, which sit next to each other
+    // in memory; points of the left part are computed where x is in
+    // [wl0, wl1) and row j-1 is in [jr0, jr1), of the right part where x is
+    // in [wr0, wr1) and row j is in [jr0, jr1)
+    int w2, wl0, wl1, wr0, wr1, jr0, jr1;
 };
 
 // BX x TY threads; thread (tx, ty) owns RY consecutive rows of VEC points.
 // Tile: TW = BX*VEC points by TH = TY*RY rows; the LDS plane tile adds one
 // halo row above and below (loaded by thread rows 0 and TY-1) and one halo
 // column left and right (loaded by lanes tx = 0 and BX-1).
-template <typename S, int VEC, int BX, int TY, int RY>
+template <typename S, int VEC, int BX, int TY, int RY, int WRAP>
 __global__ void __launch_bounds__(BX *TY)
 k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__ Ci, ZTile z,
               compute_t<S> a, compute_t<S> rx, compute_t<S> ry, compute_t<S> rz, uint32_t key,
@@ -97,7 +103,22 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
     __shared__ C tile[2][LH][LW];
 
     const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
-    int64_t g = z.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    int64_t g = blockIdx.x;
+    if (z.remap == 1) {
+        g = xcd_remap(g, gridDim.x);
+    } else if (z.remap >= 2) {
+        // keep each x-row of tiles on one XCD (work-group g runs on XCD g % 8),
+        // so neighbouring tiles read each other's edge lines from the same L2;
+        // mode 2 deals rows to XCDs in turn, mode 3 in contiguous ranges
+        const int64_t ntx0 = z.box[0].ntx;
+        const int64_t P = gridDim.x / ntx0, P8 = P / 8 * 8;
+        if (g < ntx0 * P8) {
+            const int64_t x = g % 8, slot = g / 8;
+            const int64_t q = slot / ntx0;
+            const int64_t p = z.remap == 2 ? x + 8 * q : x * (P8 / 8) + q;
+            g = slot % ntx0 + ntx0 * p;
+        }
+    }
     const int q1 = g >= z.split_block;
     if (q1) g -= z.split_block;
     const Box bb = q1 ? z.box[1].b : z.box[0].b;
@@ -132,8 +153,9 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
     const int jh = (ty == 0) ? jb - 1 : (jb + TH > ny - 1 ? ny - 1 : jb + TH);
     const int64_t colhy = (int64_t)jh * nx + i;
     const int hyrow = (ty == 0) ? 0 : LH - 1;
-    // x-halo points of this thread's rows (lanes 0 and BX-1 only)
-    const bool own_h = (tx == 0 && x0 >= 1) || (tx == BX - 1 && x0 + TW < nx);
+    // x-halo points of this thread's rows (lanes 0 and BX-1 only); a wrapped
+    // tile holds every x neighbour it needs
+    const bool own_h = !WRAP && ((tx == 0 && x0 >= 1) || (tx == BX - 1 && x0 + TW < nx));
     const int xh = (tx == 0) ? x0 - 1 : x0 + TW;
     const int hcol = (tx == 0) ? 0 : LW - 1;
 
@@ -206,11 +228,27 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
                 const C v = diffuse<C>(c, xm, xp, ym, yp, widen<C>(lane_elem<S, VEC>(tm[r], q)),
                                        widen<C>(lane_elem<S, VEC>(tp[r], q)), widen<C>(lane_elem<S, VEC>(ci[r], q)),
                                        a, rx, ry, rz);
-                const uint32_t rb = stochastic ? point_bits(pk, i + q, jr[r], nx) : 0u;
+                int ir = i + q, jreal = jr[r];
+                if (WRAP) {
+                    const bool left = ir < z.w2;
+                    ir = left ? ir + nx - z.w2 : ir - z.w2;
+                    jreal = left ? jreal - 1 : jreal;
+                }
+                const uint32_t rb = stochastic ? point_bits(pk, ir, jreal, nx) : 0u;
                 set_elem<S, VEC>(out, q, Store<S>::put(v, rb, stochastic));
             }
             S *dst = T2 + (int64_t)k * sxy + col[r];
-            if (xin && i >= bb.i0 && i + VEC <= bb.i1) {
+            if (WRAP) {
+                // VEC divides w2, so a vector lies in one part
+                const bool left = i < z.w2;
+                const int jreal = left ? jr[r] - 1 : jr[r];
+                const int c0 = left ? z.wl0 : z.wr0, c1 = left ? z.wl1 : z.wr1;
+                if (xin && jreal >= z.jr0 && jreal < z.jr1) {
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q)
+                        if (i + q >= c0 && i + q < c1) dst[q] = lane_elem<S, VEC>(out, q);
+                }
+            } else if (xin && i >= bb.i0 && i + VEC <= bb.i1) {
                 __builtin_nontemporal_store(out, reinterpret_cast<V *>(dst));
             } else if (xin) {
 #pragma unroll
@@ -259,24 +297,38 @@ int launch_step_boxes(int dtype, const StepArgs &a, const Box *b, int nb, hipStr
     return run_boxes<_Float16>(a, b, nb, s);
 }
 
-// Tile one or two boxes with TW x (BYT-2) tiles and march zc planes per
+// Tile one or two boxes with TW x TH tiles and march zc planes per
 // work-group.  Chunks of 16 planes gave the best HBM throughput on MI355X
 // at 512^3 (many short marches balance the 256 CUs; the two extra planes
-// per chunk are served from cache), and the plain work-group order beat the
-// XCD renumbering there.
-template <typename S, int VEC, int BX, int TY, int RY>
-static int run_zmarch(const StepArgs &a, const Box *b, int nbox, hipStream_t s, int zc_default = 16,
-                      const char *zc_env = "IGG_ZCHUNK")
+// per chunk are mostly served from cache).  Keeping each x-row of tiles on
+// one XCD cut the inner kernel's L2 fetches by 10% and its time by 6%.
+// Launch settings of one z-march launch: planes per work-group and the
+// work-group to XCD mapping, each with an environment override for tuning.
+struct ZLaunch {
+    int zc;
+    const char *zc_env;
+    int remap;
+    const char *remap_env;
+};
+// inner region: 16 planes, x-rows of tiles dealt to the XCDs in turn
+static const ZLaunch kInner = {16, "IGG_ZCHUNK", 2, "IGG_XCD_REMAP"};
+// x slabs: 8 planes, contiguous ranges of tile rows per XCD
+static const ZLaunch kXSlab = {8, "IGG_XSLAB_ZCHUNK", 3, "IGG_XSLAB_REMAP"};
+
+template <typename S, int VEC, int BX, int TY, int RY, int WRAP = 0>
+static int run_zmarch(const StepArgs &a, const Box *b, int nbox, hipStream_t s, const ZLaunch &L,
+                      const ZTile *wrap = nullptr)
 {
     using C = compute_t<S>;
     constexpr int TW = BX * VEC, BY = TY * RY;
     ZTile z{};
+    if (wrap) z = *wrap;
     z.nx = a.nx;
     z.ny = a.ny;
-    int zc = env_int(zc_env, zc_default);
+    int zc = env_int(L.zc_env, L.zc);
     if (zc < 1) zc = 1;
     z.zc = zc;
-    z.remap = env_int("IGG_XCD_REMAP", 0);
+    z.remap = env_int(L.remap_env, L.remap);
     int64_t blocks = 0;
     z.split_block = INT64_MAX;
     for (int q = 0; q < nbox; ++q) {
@@ -292,9 +344,11 @@ static int run_zmarch(const StepArgs &a, const Box *b, int nbox, hipStream_t s, 
     }
     if (nbox == 1) z.box[1] = z.box[0];
     if (blocks == 0) return IGG_OK;
-    hipLaunchKernelGGL((k_step_zmarch<S, VEC, BX, TY, RY>), dim3((unsigned)blocks), dim3(BX * TY), 0, s,
-                       (S *)a.T2, (const S *)a.T, (const S *)a.Ci, z, (C)a.a, (C)a.rx, (C)a.ry, (C)a.rz,
-                       a.key, a.stochastic);
+    // a wrapped tile addresses its arrays from w2 points before each row
+    const int64_t off = WRAP ? z.w2 : 0;
+    hipLaunchKernelGGL((k_step_zmarch<S, VEC, BX, TY, RY, WRAP>), dim3((unsigned)blocks), dim3(BX * TY), 0, s,
+                       (S *)a.T2 - off, (const S *)a.T - off, (const S *)a.Ci - off, z, (C)a.a, (C)a.rx, (C)a.ry,
+                       (C)a.rz, a.key, a.stochastic);
     IGG_HIP(hipGetLastError());
     return IGG_OK;
 }
@@ -315,34 +369,59 @@ static bool vec_ok(const StepArgs &a)
 int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s)
 {
     if (dtype == IGG_F64) {
-        if (vec_ok<double, 2>(a)) return run_zmarch<double, 2, 32, 16, 2>(a, &b, 1, s);
-        return run_zmarch<double, 1, 64, 8, 2>(a, &b, 1, s);
+        if (vec_ok<double, 2>(a)) return run_zmarch<double, 2, 32, 16, 2>(a, &b, 1, s, kInner);
+        return run_zmarch<double, 1, 64, 8, 2>(a, &b, 1, s, kInner);
     }
     if (dtype == IGG_F32) {
-        if (vec_ok<float, 2>(a)) return run_zmarch<float, 2, 64, 8, 2>(a, &b, 1, s);
-        return run_zmarch<float, 1, 64, 8, 2>(a, &b, 1, s);
+        if (vec_ok<float, 2>(a)) return run_zmarch<float, 2, 64, 8, 2>(a, &b, 1, s, kInner);
+        return run_zmarch<float, 1, 64, 8, 2>(a, &b, 1, s, kInner);
     }
-    if (vec_ok<_Float16, 4>(a)) return run_zmarch<_Float16, 4, 64, 8, 2>(a, &b, 1, s);
-    return run_zmarch<_Float16, 1, 64, 8, 2>(a, &b, 1, s);
+    if (vec_ok<_Float16, 4>(a)) return run_zmarch<_Float16, 4, 64, 8, 2>(a, &b, 1, s, kInner);
+    return run_zmarch<_Float16, 1, 64, 8, 2>(a, &b, 1, s, kInner);
 }
 
-// x slabs: narrow 16-point-wide tiles (one 128-byte line of FP64 per row),
-// 32 rows per tile and 8 planes per work-group, so the two slabs still give
-// a few thousand work-groups; the other slabs are whole rows or planes and
-// go through the box kernel.
+// x slabs.  When both slabs are at most 30 points wide and a row holds at
+// least 64 points, the end of row j-1 and the start of row j (adjacent in
+// memory) form one 64-point wrapped tile: one 512-byte FP64 run per row pair
+// and plane, holding every x neighbour, instead of two narrow pieces plus
+// two separate halo lines.  Otherwise narrow 16-point tiles are used.  The
+// other slabs are whole rows or planes and go through the box kernel.
+template <typename S, int VEC>
+static int run_xslabs_wrapped(const StepArgs &a, const Box &lo, const Box &hi, hipStream_t s)
+{
+    constexpr int W2 = 32;
+    ZTile z{};
+    z.w2 = W2;
+    z.wl0 = hi.i0 - a.nx + W2;
+    z.wl1 = hi.i1 - a.nx + W2;
+    z.wr0 = lo.i0 + W2;
+    z.wr1 = lo.i1 + W2;
+    z.jr0 = lo.j0;
+    z.jr1 = lo.j1;
+    Box vb{0, 2 * W2, lo.j0, lo.j1 + 1, lo.k0, lo.k1};
+    return run_zmarch<S, VEC, (2 * W2) / VEC, 16, 2, 1>(a, &vb, 1, s, kXSlab, &z);
+}
+
 static int launch_xslabs(int dtype, const StepArgs &a, const Box *b, int nb, hipStream_t s)
 {
-    const char *ev = "IGG_XSLAB_ZCHUNK";
+    // wrapped form: one slab on each side, same rows and planes, narrow enough
+    if (nb == 2 && b[0].i0 == 1 && b[1].i1 == a.nx - 1 && b[0].i1 <= 31 && a.nx - b[1].i0 <= 31 &&
+        a.nx >= 64 && b[0].j0 == b[1].j0 && b[0].j1 == b[1].j1 && b[0].k0 == b[1].k0 && b[0].k1 == b[1].k1 &&
+        b[0].j0 >= 2 && b[0].j1 <= a.ny - 2) {
+        if (dtype == IGG_F64 && vec_ok<double, 2>(a)) return run_xslabs_wrapped<double, 2>(a, b[0], b[1], s);
+        if (dtype == IGG_F32 && vec_ok<float, 2>(a)) return run_xslabs_wrapped<float, 2>(a, b[0], b[1], s);
+        if (dtype == IGG_F16 && vec_ok<_Float16, 2>(a)) return run_xslabs_wrapped<_Float16, 2>(a, b[0], b[1], s);
+    }
     if (dtype == IGG_F64) {
-        if (vec_ok<double, 2>(a)) return run_zmarch<double, 2, 8, 32, 1>(a, b, nb, s, 8, ev);
-        return run_zmarch<double, 1, 16, 16, 1>(a, b, nb, s, 8, ev);
+        if (vec_ok<double, 2>(a)) return run_zmarch<double, 2, 8, 32, 1>(a, b, nb, s, kXSlab);
+        return run_zmarch<double, 1, 16, 16, 1>(a, b, nb, s, kXSlab);
     }
     if (dtype == IGG_F32) {
-        if (vec_ok<float, 2>(a)) return run_zmarch<float, 2, 8, 32, 1>(a, b, nb, s, 8, ev);
-        return run_zmarch<float, 1, 16, 16, 1>(a, b, nb, s, 8, ev);
+        if (vec_ok<float, 2>(a)) return run_zmarch<float, 2, 8, 32, 1>(a, b, nb, s, kXSlab);
+        return run_zmarch<float, 1, 16, 16, 1>(a, b, nb, s, kXSlab);
     }
-    if (vec_ok<_Float16, 2>(a)) return run_zmarch<_Float16, 2, 8, 32, 1>(a, b, nb, s, 8, ev);
-    return run_zmarch<_Float16, 1, 16, 16, 1>(a, b, nb, s, 8, ev);
+    if (vec_ok<_Float16, 2>(a)) return run_zmarch<_Float16, 2, 8, 32, 1>(a, b, nb, s, kXSlab);
+    return run_zmarch<_Float16, 1, 16, 16, 1>(a, b, nb, s, kXSlab);
 }
 
 int launch_step_boundary(int dtype, const StepArgs &a, const Split &sp, hipStream_t s)
