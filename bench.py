@@ -144,7 +144,7 @@ def main():
     igg.update_halo(T, C)
     T0_dev = T.clone()
     dt = igg.diffusion_dt(C, lam, dx, dy, dz)
-    Wb = torch.empty_like(T)
+    Wb = T.clone()  # the second buffer starts as a copy (Fig. 1)
     log(f"timing {K} FP64 steps after {Wm} warm-up steps, split {args.split}")
     split = None if args.split == "none" else tuple(int(v) for v in args.split.split(","))
     ms, out64, k_ms, k_pts, b_ms = time_steps(igg, torch, T, Wb, C, lam, dt, dx, dy, dz, K, Wm, split)
@@ -309,6 +309,8 @@ def main():
 
     # ---------------------------------------------------------------- checkpointed adjoint
     result["variants"]["adjoint_256"] = adjoint_variant(igg, torch, synth)
+    # ---------------------------------------------------------------- small grid: eager vs graph
+    result["variants"]["c1_32_launch_bound"] = small_grid_variant(igg, torch, synth)
 
     print(json.dumps(result), flush=True)
 
@@ -361,6 +363,38 @@ def adjoint_variant(igg, torch, synth):
     torch.cuda.empty_cache()
     igg.finalize_global_grid()
     return out
+
+
+def small_grid_variant(igg, torch, synth):
+    """32^3 FP64 (the parity workload): launch-bound, so eager steps are
+    compared with replays of a captured HIP graph of the same steps."""
+    from paper_2211_15716_amd import diffusion
+    w = synth.workload("c1_32_fp64", seed=0)
+    n = w["nx"]
+    igg.init_global_grid(n, n, n, dims=(1, 1, 1), periods=(1, 1, 1), overlaps=(2, 2, 2))
+    T, C = diffusion.prepare_fields(w["T0"], w["Ci"])
+    d = (w["dx"], w["dy"], w["dz"])
+    dt = igg.diffusion_dt(C, w["lam"], *d)
+    T2 = T.clone()
+    nsteps = 200
+    diffusion.forward(T.clone(), C, 10, w["lam"], dt, *d, split=SPLIT)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    diffusion.forward(T.clone(), C, nsteps, w["lam"], dt, *d, split=SPLIT)
+    torch.cuda.synchronize()
+    eager = (time.perf_counter() - t0) * 1e3 / nsteps
+    g = diffusion.StepGraph(T, T2, C, w["lam"], dt, *d, split=SPLIT, pairs=10)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nsteps // g.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    graph = (time.perf_counter() - t0) * 1e3 / nsteps
+    igg.finalize_global_grid()
+    log(f"32^3: eager {eager*1e3:.1f} us/step, graph {graph*1e3:.1f} us/step")
+    return {"grid": [n, n, n], "split": list(SPLIT), "eager_us_per_step": round(eager * 1e3, 2),
+            "graph_us_per_step": round(graph * 1e3, 2), "steps_per_s_graph": round(1e3 / graph, 1)}
 
 
 if __name__ == "__main__":

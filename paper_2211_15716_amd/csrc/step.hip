@@ -312,6 +312,8 @@ struct ZLaunch {
 };
 // inner region: 16 planes, x-rows of tiles dealt to the XCDs in turn
 static const ZLaunch kInner = {16, "IGG_ZCHUNK", 2, "IGG_XCD_REMAP"};
+// FP16 inner region: 16 planes, contiguous ranges of tile rows per XCD
+static const ZLaunch kInnerF16 = {16, "IGG_ZCHUNK", 3, "IGG_XCD_REMAP"};
 // x slabs: 8 planes, contiguous ranges of tile rows per XCD
 static const ZLaunch kXSlab = {8, "IGG_XSLAB_ZCHUNK", 3, "IGG_XSLAB_REMAP"};
 
@@ -362,10 +364,11 @@ static bool vec_ok(const StepArgs &a)
     return a.nx % VEC == 0 && aligned(a.T, vb) && aligned(a.T2, vb) && aligned(a.Ci, vb);
 }
 
-// Inner region: tiles whose rows are 512 bytes wide (64 FP64, 128 FP32 or
-// 256 FP16 points, 16- or 8-byte loads per lane), two rows per thread; these
-// shapes gave the highest HBM throughput on MI355X at 512^3.  Rows whose
-// length does not allow vector loads take the one-point-per-lane kernel.
+// Inner region.  FP64: 64-point (512-byte) tile rows, 16-byte loads, two
+// rows per thread, 32 rows per tile.  FP32: 256-point (1 KB) rows, 16-byte
+// loads, 8 rows.  FP16: 256-point (512-byte) rows, 8-byte loads, 16 rows.
+// These shapes and work-group mappings measured fastest on MI355X at 512^3.
+// Rows whose length does not allow vector loads take one point per lane.
 int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s)
 {
     if (dtype == IGG_F64) {
@@ -373,11 +376,11 @@ int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s)
         return run_zmarch<double, 1, 64, 8, 2>(a, &b, 1, s, kInner);
     }
     if (dtype == IGG_F32) {
-        if (vec_ok<float, 2>(a)) return run_zmarch<float, 2, 64, 8, 2>(a, &b, 1, s, kInner);
+        if (vec_ok<float, 4>(a)) return run_zmarch<float, 4, 64, 8, 1>(a, &b, 1, s, kInner);
         return run_zmarch<float, 1, 64, 8, 2>(a, &b, 1, s, kInner);
     }
-    if (vec_ok<_Float16, 4>(a)) return run_zmarch<_Float16, 4, 64, 8, 2>(a, &b, 1, s, kInner);
-    return run_zmarch<_Float16, 1, 64, 8, 2>(a, &b, 1, s, kInner);
+    if (vec_ok<_Float16, 4>(a)) return run_zmarch<_Float16, 4, 64, 8, 2>(a, &b, 1, s, kInnerF16);
+    return run_zmarch<_Float16, 1, 64, 8, 2>(a, &b, 1, s, kInnerF16);
 }
 
 // x slabs.  When both slabs are at most 30 points wide and a row holds at

@@ -33,10 +33,14 @@ def forward(T, Ci, nt, lam, dt, dx, dy, dz, split=(16, 2, 2), work=None, sr_seed
             stream=None):
     """nt steps of the Fig. 1 time loop starting from T (valid halo).  Returns
     the tensor holding the final state, which is either T or `work` (the two
-    buffers are swapped each step, as in the listing).  FP16 fields round
+    buffers are swapped each step, as in the listing; a given `work` must
+    hold T's halo planes in non-periodic dimensions).  FP16 fields round
     their stores stochastically when sr_seed is given, with counter
     counter0 + step."""
-    T2 = torch.empty_like(T) if work is None else work
+    # Fig. 1 starts the second buffer as a copy of the first: halo planes of
+    # non-periodic dimensions are never written by the step, so both buffers
+    # must carry them from the start
+    T2 = T.clone() if work is None else work
     a, b = T, T2
     for it in range(nt):
         rnd = None
@@ -73,7 +77,7 @@ class Sweep:
     def __init__(self, prob, Ci, T0, ops):
         self.p, self.Ci, self.ops = prob, Ci, ops
         self.store = {0: T0}
-        self.work = [torch.empty_like(T0), torch.empty_like(T0)]
+        self.work = [T0.clone(), T0.clone()]  # halo planes of non-periodic dimensions
         self.cur, self.cur_n = T0, 0
         self.advances = 0
         self.adjoints = 0
@@ -196,3 +200,30 @@ def loss_and_grad(T0, Ci, T_obs, prob, nt, schedule=("store_all",)):
     igg.update_halo(lam_nt)
     gT0, gCi = sweep.reverse(lam_nt)
     return L, _inner_only(gT0), _inner_only(gCi), sweep
+
+
+# --------------------------------------------------------------------------- graph capture
+class StepGraph:
+    """A HIP graph holding 2*pairs consecutive diffusion steps T -> T2 -> T,
+    for grids small enough that launch latency dominates (each step is a
+    handful of short launches on two streams).  Replaying it advances the
+    state held in T by 2*pairs steps, with the same bits as the eager calls.
+
+    The step's fork and join events make it capturable across the helper
+    stream.  The library's device resources are created before capture (the
+    halo update of T below is idempotent: T carries a valid halo), since
+    nothing may be allocated while a graph is being captured."""
+
+    def __init__(self, T, T2, Ci, lam, dt, dx, dy, dz, split=(16, 2, 2), pairs=1):
+        self.T, self.T2, self.Ci = T, T2, Ci
+        igg.update_halo(T)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            for _ in range(pairs):
+                igg.diffusion_step(T2, T, Ci, lam, dt, dx, dy, dz, split=split)
+                igg.diffusion_step(T, T2, Ci, lam, dt, dx, dy, dz, split=split)
+        self.steps = 2 * pairs
+
+    def replay(self):
+        self.graph.replay()
