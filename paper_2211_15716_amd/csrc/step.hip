@@ -83,8 +83,10 @@ struct ZTile {
     // row j-1 and the first w2 points of row j, which sit next to each other
     // in memory; points of the left part are computed where x is in
     // [wl0, wl1) and row j-1 is in [jr0, jr1), of the right part where x is
-    // in [wr0, wr1) and row j is in [jr0, jr1)
-    int w2, wl0, wl1, wr0, wr1, jr0, jr1;
+    // in [wr0, wr1) and row j is in [jr0, jr1).  With wh set the tile also
+    // loads its outer x neighbours: x = -1 is column nx-w2-1 of row j-1 and
+    // x = 2*w2 is column w2 of row j (slabs a full half tile wide).
+    int w2, wl0, wl1, wr0, wr1, jr0, jr1, wh;
 };
 
 // BX x TY threads; thread (tx, ty) owns RY consecutive rows of VEC points.
@@ -154,8 +156,9 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
     const int64_t colhy = (int64_t)jh * nx + i;
     const int hyrow = (ty == 0) ? 0 : LH - 1;
     // x-halo points of this thread's rows (lanes 0 and BX-1 only); a wrapped
-    // tile holds every x neighbour it needs
-    const bool own_h = !WRAP && ((tx == 0 && x0 >= 1) || (tx == BX - 1 && x0 + TW < nx));
+    // tile needs them only when a slab fills its half tile
+    const bool own_h = WRAP ? (z.wh && (tx == 0 || tx == BX - 1))
+                            : ((tx == 0 && x0 >= 1) || (tx == BX - 1 && x0 + TW < nx));
     const int xh = (tx == 0) ? x0 - 1 : x0 + TW;
     const int hcol = (tx == 0) ? 0 : LW - 1;
 
@@ -383,16 +386,15 @@ int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s)
     return run_zmarch<_Float16, 1, 64, 8, 2>(a, &b, 1, s, kInnerF16);
 }
 
-// x slabs.  When both slabs are at most 30 points wide and a row holds at
-// least 64 points, the end of row j-1 and the start of row j (adjacent in
-// memory) form one 64-point wrapped tile: one 512-byte FP64 run per row pair
-// and plane, holding every x neighbour, instead of two narrow pieces plus
-// two separate halo lines.  Otherwise narrow 16-point tiles are used.  The
-// other slabs are whole rows or planes and go through the box kernel.
-template <typename S, int VEC>
+// x slabs.  The end of row j-1 and the start of row j sit next to each
+// other in memory, so the two x slabs of neighbouring rows form one wrapped
+// tile of 2*W2 points (W2 = 32 or 64): one contiguous run per row pair and
+// plane holding every x neighbour, instead of two narrow pieces plus two
+// separate halo lines.  Wider slabs or short rows take narrow 16-point
+// tiles.  The other slabs are whole rows or planes (box kernel).
+template <typename S, int VEC, int W2>
 static int run_xslabs_wrapped(const StepArgs &a, const Box &lo, const Box &hi, hipStream_t s)
 {
-    constexpr int W2 = 32;
     ZTile z{};
     z.w2 = W2;
     z.wl0 = hi.i0 - a.nx + W2;
@@ -401,19 +403,28 @@ static int run_xslabs_wrapped(const StepArgs &a, const Box &lo, const Box &hi, h
     z.wr1 = lo.i1 + W2;
     z.jr0 = lo.j0;
     z.jr1 = lo.j1;
+    z.wh = (z.wl0 == 0 || z.wr1 == 2 * W2) ? 1 : 0;
     Box vb{0, 2 * W2, lo.j0, lo.j1 + 1, lo.k0, lo.k1};
-    return run_zmarch<S, VEC, (2 * W2) / VEC, 16, 2, 1>(a, &vb, 1, s, kXSlab, &z);
+    return run_zmarch<S, VEC, (2 * W2) / VEC, (W2 == 64 ? 8 : 16), 2, 1>(a, &vb, 1, s, kXSlab, &z);
 }
 
 static int launch_xslabs(int dtype, const StepArgs &a, const Box *b, int nb, hipStream_t s)
 {
-    // wrapped form: one slab on each side, same rows and planes, narrow enough
-    if (nb == 2 && b[0].i0 == 1 && b[1].i1 == a.nx - 1 && b[0].i1 <= 31 && a.nx - b[1].i0 <= 31 &&
-        a.nx >= 64 && b[0].j0 == b[1].j0 && b[0].j1 == b[1].j1 && b[0].k0 == b[1].k0 && b[0].k1 == b[1].k1 &&
-        b[0].j0 >= 2 && b[0].j1 <= a.ny - 2) {
-        if (dtype == IGG_F64 && vec_ok<double, 2>(a)) return run_xslabs_wrapped<double, 2>(a, b[0], b[1], s);
-        if (dtype == IGG_F32 && vec_ok<float, 2>(a)) return run_xslabs_wrapped<float, 2>(a, b[0], b[1], s);
-        if (dtype == IGG_F16 && vec_ok<_Float16, 2>(a)) return run_xslabs_wrapped<_Float16, 2>(a, b[0], b[1], s);
+    // wrapped form: one slab on each side, same rows and planes; the slabs
+    // end at most w2 points from the row's ends (w = the larger distance)
+    if (nb == 2 && b[0].i0 == 1 && b[1].i1 == a.nx - 1 && b[0].j0 == b[1].j0 && b[0].j1 == b[1].j1 &&
+        b[0].k0 == b[1].k0 && b[0].k1 == b[1].k1 && b[0].j0 >= 2 && b[0].j1 <= a.ny - 2) {
+        const int w = std::max(b[0].i1, a.nx - b[1].i0);
+        if (w <= 31 && a.nx >= 64) {
+            if (dtype == IGG_F64 && vec_ok<double, 2>(a)) return run_xslabs_wrapped<double, 2, 32>(a, b[0], b[1], s);
+            if (dtype == IGG_F32 && vec_ok<float, 2>(a)) return run_xslabs_wrapped<float, 2, 32>(a, b[0], b[1], s);
+            if (dtype == IGG_F16 && vec_ok<_Float16, 2>(a)) return run_xslabs_wrapped<_Float16, 2, 32>(a, b[0], b[1], s);
+        }
+        if (w <= 64 && a.nx >= 130) {
+            if (dtype == IGG_F64 && vec_ok<double, 2>(a)) return run_xslabs_wrapped<double, 2, 64>(a, b[0], b[1], s);
+            if (dtype == IGG_F32 && vec_ok<float, 2>(a)) return run_xslabs_wrapped<float, 2, 64>(a, b[0], b[1], s);
+            if (dtype == IGG_F16 && vec_ok<_Float16, 2>(a)) return run_xslabs_wrapped<_Float16, 2, 64>(a, b[0], b[1], s);
+        }
     }
     if (dtype == IGG_F64) {
         if (vec_ok<double, 2>(a)) return run_zmarch<double, 2, 8, 32, 1>(a, b, nb, s, kXSlab);

@@ -128,6 +128,34 @@ def test_split_equals_unsplit_bit_exact(dt_name):
             assert np.array_equal(o, outs[0])
 
 
+@pytest.mark.parametrize("n", [(260, 40, 20), (300, 35, 19)])
+@pytest.mark.parametrize("dt_name", ["f64", "f32", "f16"])
+def test_wide_rows_split_forms(n, dt_name):
+    """Rows of a few hundred points: x slabs up to 31 points wide take the
+    64-point wrapped tiles, 32 to 64 points the 128-point wrapped tiles with
+    their outer x neighbours; every result equals the unsplit step, and FP64
+    the oracle."""
+    nx, ny, nz = n
+    T0, Ci = synth.noisy_state_uniform_ci(nx, ny, nz, seed=19, noise=1e-2)
+    oracle.halo(T0)
+    oracle.halo(Ci)
+    dx = 1.0 / (nx - 1)
+    dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
+    ref = oracle.run(T0, Ci, 4, 1.0, dt, dx, dx, dx) if dt_name == "f64" else None
+    outs = []
+    with grid(n):
+        T, C = dev(T0, DT[dt_name]), dev(Ci, DT[dt_name])
+        for split in [None, (16, 2, 2), (64, 2, 2), (40, 2, 2), (63, 2, 3), (31, 2, 2), (32, 2, 2), (2, 5, 3)]:
+            say("wide rows", n, dt_name, split)
+            o = diffusion.forward(T.clone(), C, 4, 1.0, dt, dx, dx, dx, split=split,
+                                  sr_seed=7 if dt_name == "f16" else None)
+            outs.append(host(o))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    if ref is not None:
+        assert rel_max_err(outs[0], ref) <= 1e-12
+
+
 @pytest.mark.parametrize("dt_name", ["f64", "f32", "f16"])
 def test_constant_state_exact_all_dtypes(dt_name):
     """Fig. 1's own state (T = 1.7, Ci = 1/c0) never changes, in any precision."""
