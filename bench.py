@@ -82,38 +82,49 @@ def traffic_from_profiles(kernel_hash, key):
 
 
 def time_steps(igg, torch, T, W, C, lam, dt, dx, dy, dz, steps, warmup, split, rnd_seed=None):
-    """Warm up, then time `steps` diffusion steps; returns (ms/step, final
-    buffer, inner-kernel ms/launch, inner points/launch, boundary-kernel ms
-    per step)."""
+    """Warm up, then time `steps` diffusion steps twice: a plain pass (the
+    step time) and a pass with the library's kernel timing events on the
+    streams the kernels run on (the inner-kernel and boundary durations).
+    Returns (ms/step, final buffer of the plain pass, inner-kernel
+    ms/launch, inner points/launch, boundary-kernel ms per step, ms/step of
+    the instrumented pass)."""
     a, b = T, W
+    it = 0
 
-    def one(it):
-        nonlocal a, b
+    def one():
+        nonlocal a, b, it
         rnd = igg.rounding("stochastic", rnd_seed, it) if rnd_seed is not None else None
         igg.diffusion_step(b, a, C, lam, dt, dx, dy, dz, split=split, rnd=rnd)
         a, b = b, a
+        it += 1
 
-    for it in range(warmup):
-        one(it)
-    torch.cuda.synchronize()
+    def timed():
+        s0 = torch.cuda.Event(enable_timing=True)
+        s1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s0.record()
+        for _ in range(steps):
+            one()
+        s1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return max(wall * 1e3, s0.elapsed_time(s1)) / steps
+
+    for _ in range(warmup):
+        one()
+    ms = timed()
+    final = a
+    if steps > 0:
+        # the instrumented pass continues from the final state in fresh buffers
+        a, b = a.clone(), b.clone()
     igg.timing_read()  # discard
     igg.timing_enable(True)
-    s0 = torch.cuda.Event(enable_timing=True)
-    s1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s0.record()
-    for it in range(warmup, warmup + steps):
-        one(it)
-    s1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    ms_inst = timed()
     igg.timing_enable(False)
     k_ms, k_launches, k_points, b_ms = igg.timing_read()
-    ev_ms = s0.elapsed_time(s1)
-    ms = max(wall * 1e3, ev_ms) / steps
     per_launch = k_ms / max(1, k_launches)
-    return ms, a, per_launch, (k_points // max(1, k_launches)), b_ms / steps
+    return ms, final, per_launch, (k_points // max(1, k_launches)), b_ms / max(1, steps), ms_inst
 
 
 def main():
@@ -147,15 +158,12 @@ def main():
     Wb = T.clone()  # the second buffer starts as a copy (Fig. 1)
     log(f"timing {K} FP64 steps after {Wm} warm-up steps, split {args.split}")
     split = None if args.split == "none" else tuple(int(v) for v in args.split.split(","))
-    ms, out64, k_ms, k_pts, b_ms = time_steps(igg, torch, T, Wb, C, lam, dt, dx, dy, dz, K, Wm, split)
+    ms, out64, k_ms, k_pts, b_ms, ms_inst = time_steps(igg, torch, T, Wb, C, lam, dt, dx, dy, dz, K, Wm, split)
     teff = 24.0 * pts / (ms * 1e-3) / 1e9
     k_bytes = 24.0 * k_pts
     k_gbs = k_bytes / (k_ms * 1e-3) / 1e9
     khash = kernel_source_hash()
     traffic = traffic_from_profiles(khash, "inner_step_f64_512")
-    # the halo update runs beside the inner kernel: its cost is what the step
-    # takes beyond the boundary and inner kernels on the caller stream
-    halo_overhead = ms / (k_ms + b_ms) - 1.0 if (k_ms > 0 and split is not None) else None
     log(f"FP64: {ms:.4f} ms/step, T_eff {teff:.1f} GB/s; inner kernel {k_ms:.4f} ms, {k_gbs:.1f} GB/s")
 
     result = {
@@ -173,8 +181,9 @@ def main():
                      "frac": round(k_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": k_bytes, "points_per_launch": k_pts,
                      "ms_per_launch": round(k_ms, 5), "kernel_source_hash": khash},
-        "halo_overhead": None if halo_overhead is None else round(halo_overhead, 4),
+        "halo_overhead": None,
         "boundary_ms_per_step": round(b_ms, 5),
+        "ms_per_step_instrumented": round(ms_inst, 5),
     }
 
     if args.profile:
@@ -206,9 +215,14 @@ def main():
 
     # ---------------------------------------------------------------- unsplit FP64 for comparison
     T = T0_dev.clone()
-    ms_u, _, _, _, _ = time_steps(igg, torch, T, Wb, C, lam, dt, dx, dy, dz, min(K, 50), 5, None)
+    ms_u, _, ku_ms, ku_pts, _, _ = time_steps(igg, torch, T, Wb, C, lam, dt, dx, dy, dz, min(K, 50), 5, None)
     result["variants"] = {"f64_unsplit": {"ms_per_step": round(ms_u, 5),
-                                          "T_eff_GBs": round(24.0 * pts / (ms_u * 1e-3) / 1e9, 1)}}
+                                          "T_eff_GBs": round(24.0 * pts / (ms_u * 1e-3) / 1e9, 1),
+                                          "kernel_ms": round(ku_ms, 5)}}
+    # the halo update's step-time overhead: the split step against the step
+    # kernel over all inner points alone (the same computation, no update)
+    if split is not None and ku_pts == (n - 2) ** 3:
+        result["halo_overhead"] = round(ms / ku_ms - 1.0, 4)
 
     # ---------------------------------------------------------------- CPU oracle baseline
     gpu64 = None
@@ -220,7 +234,7 @@ def main():
         oracle.halo(Cih)
         # the GPU result after exactly oracle_nt steps, for a full-field error
         T = T0_dev.clone()
-        ms_chk, gout, _, _, _ = time_steps(igg, torch, T, Wb, C, lam, dt, dx, dy, dz, oracle_nt, 0, SPLIT)
+        ms_chk, gout, _, _, _, _ = time_steps(igg, torch, T, Wb, C, lam, dt, dx, dy, dz, oracle_nt, 0, SPLIT)
         gpu64 = gout.cpu().numpy()
         log(f"oracle: up to {oracle_nt} steps of the {n}^3 FP64 workload on the host")
         cur, nxt = T0h, np.empty_like(T0h)
@@ -279,8 +293,8 @@ def main():
         else:
             d = (final - ref)[1:-1, 1:-1, 1:-1].abs().max().item()
             err = d / ref[1:-1, 1:-1, 1:-1].abs().max().item()
-        msv, _, kv_ms, kv_pts, _ = time_steps(igg, torch, Tv.clone(), Wv, Cv, lam, dt3, dx, dy, dz, K, Wm, SPLIT,
-                                           rnd_seed=seed)
+        msv, _, kv_ms, kv_pts, _, _ = time_steps(igg, torch, Tv.clone(), Wv, Cv, lam, dt3, dx, dy, dz, K, Wm,
+                                                 SPLIT, rnd_seed=seed)
         s = Tv.element_size()
         entry = {"ms_per_step": round(msv, 5), "T_eff_GBs": round(3 * s * pts / (msv * 1e-3) / 1e9, 1),
                  "hbm_frac": round(3 * s * pts / (msv * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

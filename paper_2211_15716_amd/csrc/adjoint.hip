@@ -297,8 +297,8 @@ static int run_zmarch(const AdjArgs &a, const Box &b, hipStream_t s)
     z.ntx = (b.i1 - z.xa + TW - 1) / TW;
     z.nty = (b.j1 - b.j0 + TH - 1) / TH;
     int depth = b.k1 - b.k0;
-    int zc = env_int("IGG_ADJ_ZCHUNK", 16);
-    if (zc < 1) zc = 1;
+    int zc = env_int("IGG_ADJ_ZCHUNK", 0);
+    if (zc < 1) zc = auto_zchunk((int64_t)z.ntx * z.nty, depth, 16);
     z.zc = zc;
     z.remap = env_int("IGG_ADJ_REMAP", 2);
     int64_t blocks = (int64_t)z.ntx * z.nty * ((depth + zc - 1) / zc);
@@ -325,6 +325,7 @@ static bool vec2_ok(const AdjArgs &a)
 // lane where the row length does not allow 16-byte loads.
 int launch_adjoint_inner(int dtype, const AdjArgs &a, const Box &b, hipStream_t s)
 {
+    if (box_count(b) < zmarch_min_points()) return launch_adjoint_boxes(dtype, a, &b, 1, s);
     if (dtype == IGG_F64)
         return vec2_ok<double>(a) ? run_zmarch<double, 2, 32, 16, 1>(a, b, s) : run_zmarch<double, 1, 64, 8, 2>(a, b, s);
     return vec2_ok<float>(a) ? run_zmarch<float, 2, 64, 8, 1>(a, b, s) : run_zmarch<float, 1, 64, 8, 2>(a, b, s);

@@ -34,6 +34,8 @@ Grid &grid()
     return g;
 }
 
+int64_t zmarch_min_points() { return grid().zmarch_min; }
+
 int elem_bytes(int dtype) { return dtype == IGG_F64 ? 8 : dtype == IGG_F32 ? 4 : 2; }
 
 int64_t field_elems(const igg_field &f) { return f.size[0] * f.size[1] * f.size[2]; }
@@ -138,8 +140,11 @@ int ensure_device()
     }
     // default priority: the helper stream is an ordinary second stream
     IGG_HIP(hipStreamCreateWithFlags(&g.side, hipStreamNonBlocking));
-    IGG_HIP(hipEventCreateWithFlags(&g.ev_fork, hipEventDisableTiming));
-    IGG_HIP(hipEventCreateWithFlags(&g.ev_join, hipEventDisableTiming));
+    // fork/join events order work between two streams of this device only:
+    // no timing and no system-scope fence (a fence writes back the caches
+    // at every record, tens of microseconds per step at 512^3)
+    IGG_HIP(hipEventCreateWithFlags(&g.ev_fork, hipEventDisableTiming | hipEventDisableSystemFence));
+    IGG_HIP(hipEventCreateWithFlags(&g.ev_join, hipEventDisableTiming | hipEventDisableSystemFence));
     // one plane of the largest field (n+1 per dimension) in FP64, rounded to 256 B
     int64_t m0 = (int64_t)(g.n[1] + 1) * (g.n[2] + 1), m1 = (int64_t)(g.n[0] + 1) * (g.n[2] + 1),
             m2 = (int64_t)(g.n[0] + 1) * (g.n[1] + 1);
@@ -181,8 +186,10 @@ static int timing_mark(hipStream_t s, int kind)
     Grid &g = grid();
     if (!g.timing) return IGG_OK;
     if (g.tev_used == g.tev.size()) {
+        // timing only: no system-scope fence, which would add a cache
+        // write-back to the work being timed
         hipEvent_t e;
-        IGG_HIP(hipEventCreate(&e));
+        IGG_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
         g.tev.push_back(e);
         g.tev_kind.push_back(0);
     }
@@ -195,6 +202,11 @@ static int64_t box_points(const Box &b)
 {
     return (int64_t)std::max(0, b.i1 - b.i0) * std::max(0, b.j1 - b.j0) * std::max(0, b.k1 - b.k0);
 }
+
+// inner regions of at least this many points run the boundary slabs and the
+// halo update on the helper stream by default, smaller ones in one chain on
+// the caller stream
+static const int64_t kSideMinPoints = (int64_t)1 << 21;
 
 static int check_split(const int *split, const int *ol)
 {
@@ -262,7 +274,11 @@ int igg_init_global_grid(int nx, int ny, int nz, const int dims[3], const int pe
     g.timing = false;
     {
         const char *e = getenv("IGG_SCHEDULE");
-        g.schedule = (e && *e) ? atoi(e) : 0;
+        g.schedule = (e && *e) ? atoi(e) : -1;
+        const char *x = getenv("IGG_X_EXCHANGE");
+        g.fuse_x = !(x && strcmp(x, "halo") == 0);
+        const char *zm = getenv("IGG_ZMARCH_MIN_POINTS");
+        g.zmarch_min = (zm && *zm) ? atoll(zm) : kZmarchMinPoints;
     }
     g.tev_used = 0;
     g.t_launches = g.t_points = 0;
@@ -372,46 +388,78 @@ int diffusion_step(const igg_field *T2, const igg_field *T, const igg_field *Ci,
     if ((rc = ensure_device())) return rc;
 
     hipStream_t s = (hipStream_t)stream;
+    // With x periodic the step kernels also store the x halo of T2 (the
+    // exchange with this process as its own neighbour is a copy of the two
+    // source columns, fused into the kernels that compute them); the halo
+    // update then moves the y and z planes only.
+    const XHalo xh{(g.fuse_x && g.periods[0]) ? 1 : 0, g.ol[0] - 1, g.n[0] - g.ol[0]};
+    const int halo_dims = xh.on ? 6 : 7;
     StepArgs a{T2->data, T->data, Ci->data, g.n[0], g.n[1], g.n[2],
-               dt * lam, 1.0 / (dx * dx), 1.0 / (dy * dy), 1.0 / (dz * dz), key, stochastic};
+               dt * lam, 1.0 / (dx * dx), 1.0 / (dy * dy), 1.0 / (dz * dz), key, stochastic, xh};
     if (!split) {
         Box all{1, g.n[0] - 1, 1, g.n[1] - 1, 1, g.n[2] - 1};
         if ((rc = timing_mark(s, 0))) return rc;
         if ((rc = launch_step_inner(T->dtype, a, all, s))) return rc;
         if ((rc = timing_mark(s, 0))) return rc;
         if (g.timing) { g.t_launches++; g.t_points += box_points(all); }
-        return launch_halo(T2, 1, s);
+        return launch_halo(T2, 1, s, halo_dims);
     }
-    // boundary first: the slabs on the caller stream, then the halo update of
-    // T2 on the helper stream while the inner region runs on the caller stream
+    // Boundary first: the slabs the halo update reads, then the update of T2.
+    // Schedule 1 runs both on the helper stream while the inner region runs
+    // on the caller stream (as hide_communication does with its boundary
+    // streams); schedule 0 runs the slabs on the caller stream ahead of the
+    // inner region and only the update beside it; schedule 2 runs slabs,
+    // update and inner region in that order on the caller stream.  By
+    // default large inner regions take schedule 1; small grids are
+    // launch-bound, the cross-stream fork and join cost more than the update
+    // they would hide, and a captured graph of a single chain replays
+    // fastest, so they take schedule 2.  When the x exchange is fused into
+    // the stores (or x is not periodic) the update never reads the x slabs,
+    // so they join the inner launch and the boundary phase is the y and z
+    // slabs.
     Split sp;
     plan_split(g.n, split, sp);
-    const int sched = g.schedule;
-    Split main_part = sp, side_part = sp;
-    main_part.nb = side_part.nb = 0;
-    for (int q = 0; q < sp.nb; ++q) {
-        bool on_side = sched == 1 || (sched == 2 && sp.kind[q] == 0);
-        Split &dst = on_side ? side_part : main_part;
-        dst.boundary[dst.nb] = sp.boundary[q];
-        dst.kind[dst.nb++] = sp.kind[q];
+    Split bnd = sp;
+    Box inner = sp.inner;
+    if (g.fuse_x) {
+        bnd.nb = 0;
+        for (int q = 0; q < sp.nb; ++q) {
+            if (sp.kind[q] == 0) continue;
+            bnd.boundary[bnd.nb] = sp.boundary[q];
+            bnd.kind[bnd.nb++] = sp.kind[q];
+        }
+        inner.i0 = 1;
+        inner.i1 = g.n[0] - 1;
     }
-    if (main_part.nb) {
-        if ((rc = timing_mark(s, 1))) return rc;
-        if ((rc = launch_step_boundary(T->dtype, a, main_part, s))) return rc;
-        if ((rc = timing_mark(s, 1))) return rc;
+    const int sched = g.schedule >= 0 ? g.schedule : (box_points(inner) >= kSideMinPoints ? 1 : 2);
+    const bool on_side = sched == 1, serial = sched == 2;
+    hipStream_t bs = on_side ? g.side : s;
+    if (on_side) {
+        IGG_HIP(hipEventRecord(g.ev_fork, s));
+        IGG_HIP(hipStreamWaitEvent(g.side, g.ev_fork, 0));
     }
-    IGG_HIP(hipEventRecord(g.ev_fork, s));
-    IGG_HIP(hipStreamWaitEvent(g.side, g.ev_fork, 0));
-    if (side_part.nb && (rc = launch_step_boundary(T->dtype, a, side_part, g.side))) return rc;
-    if ((rc = launch_halo(T2, 1, g.side))) return rc;
-    IGG_HIP(hipEventRecord(g.ev_join, g.side));
-    if (box_points(sp.inner) > 0) {
+    if (bnd.nb) {
+        if ((rc = timing_mark(bs, 1))) return rc;
+        if ((rc = launch_step_boundary(T->dtype, a, bnd, bs))) return rc;
+        if ((rc = timing_mark(bs, 1))) return rc;
+    }
+    if (serial) {
+        if ((rc = launch_halo(T2, 1, s, halo_dims))) return rc;
+    } else {
+        if (!on_side) {
+            IGG_HIP(hipEventRecord(g.ev_fork, s));
+            IGG_HIP(hipStreamWaitEvent(g.side, g.ev_fork, 0));
+        }
+        if ((rc = launch_halo(T2, 1, g.side, halo_dims))) return rc;
+        IGG_HIP(hipEventRecord(g.ev_join, g.side));
+    }
+    if (box_points(inner) > 0) {
         if ((rc = timing_mark(s, 0))) return rc;
-        if ((rc = launch_step_inner(T->dtype, a, sp.inner, s))) return rc;
+        if ((rc = launch_step_inner(T->dtype, a, inner, s))) return rc;
         if ((rc = timing_mark(s, 0))) return rc;
-        if (g.timing) { g.t_launches++; g.t_points += box_points(sp.inner); }
+        if (g.timing) { g.t_launches++; g.t_points += box_points(inner); }
     }
-    IGG_HIP(hipStreamWaitEvent(s, g.ev_join, 0));
+    if (!serial) IGG_HIP(hipStreamWaitEvent(s, g.ev_join, 0));
     return IGG_OK;
 }
 

@@ -74,11 +74,12 @@ static unsigned char *recv_buf(Grid &g, int f, int side)
     return g.halo_buf + (size_t)(2 * IGG_MAX_FIELDS + f * 2 + side) * g.halo_cap;
 }
 
-int launch_halo(const igg_field *fl, int nf, hipStream_t s)
+int launch_halo(const igg_field *fl, int nf, hipStream_t s, int dims)
 {
     Grid &g = grid();
     for (int d = 0; d < 3; ++d) {
         if (!g.periods[d]) continue;  // no neighbour in this dimension
+        if (!((dims >> d) & 1)) continue;  // done elsewhere (fused into the step)
         HaloSet hs{};
         int64_t maxcount = 0;
         for (int f = 0; f < nf; ++f) {

@@ -8,6 +8,8 @@
 #include <string>
 #include <vector>
 
+#include <algorithm>
+
 #include "igg.h"
 #include "device.hpp"
 
@@ -21,6 +23,28 @@ int hip_fail(hipError_t e, const char *what);
         hipError_t e_ = (call);                              \
         if (e_ != hipSuccess) return ::igg::hip_fail(e_, #call); \
     } while (0)
+
+// ------------------------------------------------------------ launch shapes
+inline int64_t box_count(const Box &b)
+{
+    return (int64_t)std::max(0, b.i1 - b.i0) * std::max(0, b.j1 - b.j0) * std::max(0, b.k1 - b.k0);
+}
+
+// Regions below zmarch_min_points() points (default 2^21) go to the
+// one-thread-per-point box kernels: their z-march tiles would be too few to
+// fill the chip, and such fields sit in the caches anyway.
+constexpr int64_t kZmarchMinPoints = (int64_t)1 << 21;
+int64_t zmarch_min_points();
+
+// Planes per z-march work-group: the largest of zc_max, zc_max/2, ... (at
+// least 4) that still gives about 2048 work-groups for `columns` tiles over
+// `depth` planes, so mid-sized grids fill the 256 compute units.
+inline int auto_zchunk(int64_t columns, int depth, int zc_max)
+{
+    int zc = zc_max;
+    while (zc > 4 && columns * ((depth + zc - 1) / zc) < 2048) zc /= 2;
+    return zc < 1 ? 1 : zc;
+}
 
 // ------------------------------------------------------------------ state
 // The one implicit global grid of the process (the paper's calls take no
@@ -44,7 +68,10 @@ struct Grid {
     double *red_part = nullptr;  // per-block partial results
     double *red_host = nullptr;  // pinned host result
 
-    int schedule = 0;  // where the boundary slabs run (0: caller stream first)
+    int schedule = -1;  // 1: slabs + update on the helper stream, 0: slabs first on the caller
+                        // stream, 2: one chain on the caller stream, -1: 1 or 2 by size
+    int fuse_x = 1;    // x exchange fused into the step kernels' stores
+    int64_t zmarch_min = kZmarchMinPoints;  // smallest region for the z-march kernels
 
     bool timing = false;
     std::vector<hipEvent_t> tev;  // start/stop pairs of timed launches
@@ -74,7 +101,16 @@ BoxSet make_boxset(const Box *b, int nb);
 
 // ------------------------------------------------------------- launchers
 // Halo update of fields (already validated) on `s`.
-int launch_halo(const igg_field *f, int nf, hipStream_t s);
+// dims: bit d set = update dimension d (x = bit 0)
+int launch_halo(const igg_field *f, int nf, hipStream_t s, int dims = 7);
+
+// x exchange fused into a step kernel: when `on`, the point computed at
+// x = lo (ol-1) is also stored at x = nx-1 and the point at x = hi (nx-ol)
+// at x = 0, which is what the periodic x halo update of the result does
+// when this process is its own x neighbour.
+struct XHalo {
+    int on, lo, hi;
+};
 
 struct StepArgs {
     void *T2;
@@ -84,6 +120,7 @@ struct StepArgs {
     double a, rx, ry, rz;  // dt*lam, 1/dx^2, 1/dy^2, 1/dz^2
     uint32_t key;          // FP16 stochastic-rounding key
     int stochastic;
+    XHalo xh;
 };
 int launch_step_boxes(int dtype, const StepArgs &a, const Box *b, int nb, hipStream_t s);
 int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s);

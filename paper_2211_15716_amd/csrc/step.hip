@@ -35,6 +35,17 @@ __device__ __forceinline__ S lane_elem(const typename VecOf<S, VEC>::type &v, in
         return v[q];
 }
 
+// element q of a vector for a q known only at run time
+template <typename S, int VEC>
+__device__ __forceinline__ S lane_elem_dyn(const typename VecOf<S, VEC>::type &v, int q)
+{
+    S x = lane_elem<S, VEC>(v, 0);
+#pragma unroll
+    for (int p = 1; p < VEC; ++p)
+        if (q == p) x = lane_elem<S, VEC>(v, p);
+    return x;
+}
+
 template <typename S, int VEC>
 __device__ __forceinline__ void set_elem(typename VecOf<S, VEC>::type &v, int q, S x)
 {
@@ -49,7 +60,7 @@ template <typename S>
 __global__ void __launch_bounds__(256)
 k_step_boxes(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__ Ci, BoxSet bs, int nx,
              int ny, compute_t<S> a, compute_t<S> rx, compute_t<S> ry, compute_t<S> rz, uint32_t key,
-             int stochastic)
+             int stochastic, XHalo xh)
 {
     using C = compute_t<S>;
     int i, j, k;
@@ -62,7 +73,12 @@ k_step_boxes(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__ 
                        widen<C>(T[p - sz]), widen<C>(T[p + sz]), widen<C>(Ci[p]), a, rx, ry, rz);
     uint32_t r = 0;
     if (stochastic) r = point_bits(plane_key(key, k), i, j, nx);
-    T2[p] = Store<S>::put(out, r, stochastic);
+    const S v = Store<S>::put(out, r, stochastic);
+    T2[p] = v;
+    if (xh.on) {
+        if (i == xh.lo) T2[p - i + nx - 1] = v;
+        if (i == xh.hi) T2[p - i] = v;
+    }
 }
 
 // --------------------------------------------------------------- z-march
@@ -87,6 +103,7 @@ struct ZTile {
     // loads its outer x neighbours: x = -1 is column nx-w2-1 of row j-1 and
     // x = 2*w2 is column w2 of row j (slabs a full half tile wide).
     int w2, wl0, wl1, wr0, wr1, jr0, jr1, wh;
+    XHalo xh;
 };
 
 // BX x TY threads; thread (tx, ty) owns RY consecutive rows of VEC points.
@@ -241,12 +258,19 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
                 set_elem<S, VEC>(out, q, Store<S>::put(v, rb, stochastic));
             }
             S *dst = T2 + (int64_t)k * sxy + col[r];
+            // dst + q is the point's own address; ix is its x index in the row
+            int ix = i;
+            bool rowin = xin;
+            int c0 = bb.i0, c1 = bb.i1;
             if (WRAP) {
                 // VEC divides w2, so a vector lies in one part
                 const bool left = i < z.w2;
                 const int jreal = left ? jr[r] - 1 : jr[r];
-                const int c0 = left ? z.wl0 : z.wr0, c1 = left ? z.wl1 : z.wr1;
-                if (xin && jreal >= z.jr0 && jreal < z.jr1) {
+                ix = left ? i + nx - z.w2 : i - z.w2;
+                rowin = xin && jreal >= z.jr0 && jreal < z.jr1;
+                c0 = left ? z.wl0 : z.wr0;
+                c1 = left ? z.wl1 : z.wr1;
+                if (rowin) {
 #pragma unroll
                     for (int q = 0; q < VEC; ++q)
                         if (i + q >= c0 && i + q < c1) dst[q] = lane_elem<S, VEC>(out, q);
@@ -257,6 +281,17 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
 #pragma unroll
                 for (int q = 0; q < VEC; ++q)
                     if (i + q >= bb.i0 && i + q < bb.i1) dst[q] = lane_elem<S, VEC>(out, q);
+            }
+            // x exchange with this process as its own neighbour (x periodic):
+            // the point at x = ol-1 also fills x = nx-1, the point at
+            // x = nx-ol also fills x = 0
+            if (z.xh.on && rowin && ix <= z.xh.lo && ix + VEC > z.xh.lo) {
+                const int q = z.xh.lo - ix;
+                if (i + q >= c0 && i + q < c1) dst[q + nx - 1 - z.xh.lo] = lane_elem_dyn<S, VEC>(out, q);
+            }
+            if (z.xh.on && rowin && ix <= z.xh.hi && ix + VEC > z.xh.hi) {
+                const int q = z.xh.hi - ix;
+                if (i + q >= c0 && i + q < c1) dst[q - z.xh.hi] = lane_elem_dyn<S, VEC>(out, q);
             }
         }
 #pragma unroll
@@ -288,7 +323,7 @@ static int run_boxes(const StepArgs &a, const Box *b, int nb, hipStream_t s)
     int64_t blocks = (threads + 255) / 256;
     hipLaunchKernelGGL(k_step_boxes<S>, dim3((unsigned)blocks), dim3(256), 0, s, (S *)a.T2,
                        (const S *)a.T, (const S *)a.Ci, bs, a.nx, a.ny, (C)a.a, (C)a.rx, (C)a.ry,
-                       (C)a.rz, a.key, a.stochastic);
+                       (C)a.rz, a.key, a.stochastic, a.xh);
     IGG_HIP(hipGetLastError());
     return IGG_OK;
 }
@@ -315,8 +350,8 @@ struct ZLaunch {
 };
 // inner region: 16 planes, x-rows of tiles dealt to the XCDs in turn
 static const ZLaunch kInner = {16, "IGG_ZCHUNK", 2, "IGG_XCD_REMAP"};
-// FP16 inner region: 16 planes, contiguous ranges of tile rows per XCD
-static const ZLaunch kInnerF16 = {16, "IGG_ZCHUNK", 3, "IGG_XCD_REMAP"};
+// FP32 and FP16 inner region: 16 planes, contiguous ranges of tile rows per XCD
+static const ZLaunch kInnerRanges = {16, "IGG_ZCHUNK", 3, "IGG_XCD_REMAP"};
 // x slabs: 8 planes, contiguous ranges of tile rows per XCD
 static const ZLaunch kXSlab = {8, "IGG_XSLAB_ZCHUNK", 3, "IGG_XSLAB_REMAP"};
 
@@ -330,8 +365,16 @@ static int run_zmarch(const StepArgs &a, const Box *b, int nbox, hipStream_t s, 
     if (wrap) z = *wrap;
     z.nx = a.nx;
     z.ny = a.ny;
-    int zc = env_int(L.zc_env, L.zc);
-    if (zc < 1) zc = 1;
+    z.xh = a.xh;
+    int64_t columns = 0;
+    int depth_max = 0;
+    for (int q = 0; q < nbox; ++q) {
+        const int xa = (b[q].i0 / VEC) * VEC;
+        columns += (int64_t)((b[q].i1 - xa + TW - 1) / TW) * ((b[q].j1 - b[q].j0 + BY - 1) / BY);
+        depth_max = std::max(depth_max, b[q].k1 - b[q].k0);
+    }
+    int zc = env_int(L.zc_env, 0);
+    if (zc < 1) zc = auto_zchunk(columns, depth_max, L.zc);
     z.zc = zc;
     z.remap = env_int(L.remap_env, L.remap);
     int64_t blocks = 0;
@@ -367,23 +410,25 @@ static bool vec_ok(const StepArgs &a)
     return a.nx % VEC == 0 && aligned(a.T, vb) && aligned(a.T2, vb) && aligned(a.Ci, vb);
 }
 
-// Inner region.  FP64: 64-point (512-byte) tile rows, 16-byte loads, two
-// rows per thread, 32 rows per tile.  FP32: 256-point (1 KB) rows, 16-byte
-// loads, 8 rows.  FP16: 256-point (512-byte) rows, 8-byte loads, 16 rows.
+// Inner region.  FP64: 128-point (1 KB) tile rows, 16-byte loads, four
+// rows per thread, 16 rows per tile.  FP32: 256-point (1 KB) rows, 16-byte
+// loads, two rows per thread, 16 rows.  FP16: 256-point (512-byte) rows,
+// 8-byte loads, 16 rows.
 // These shapes and work-group mappings measured fastest on MI355X at 512^3.
 // Rows whose length does not allow vector loads take one point per lane.
 int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s)
 {
+    if (box_count(b) < zmarch_min_points()) return launch_step_boxes(dtype, a, &b, 1, s);
     if (dtype == IGG_F64) {
-        if (vec_ok<double, 2>(a)) return run_zmarch<double, 2, 32, 16, 2>(a, &b, 1, s, kInner);
+        if (vec_ok<double, 2>(a)) return run_zmarch<double, 2, 64, 4, 4>(a, &b, 1, s, kInner);
         return run_zmarch<double, 1, 64, 8, 2>(a, &b, 1, s, kInner);
     }
     if (dtype == IGG_F32) {
-        if (vec_ok<float, 4>(a)) return run_zmarch<float, 4, 64, 8, 1>(a, &b, 1, s, kInner);
+        if (vec_ok<float, 4>(a)) return run_zmarch<float, 4, 64, 8, 2>(a, &b, 1, s, kInnerRanges);
         return run_zmarch<float, 1, 64, 8, 2>(a, &b, 1, s, kInner);
     }
-    if (vec_ok<_Float16, 4>(a)) return run_zmarch<_Float16, 4, 64, 8, 2>(a, &b, 1, s, kInnerF16);
-    return run_zmarch<_Float16, 1, 64, 8, 2>(a, &b, 1, s, kInnerF16);
+    if (vec_ok<_Float16, 4>(a)) return run_zmarch<_Float16, 4, 64, 8, 2>(a, &b, 1, s, kInnerRanges);
+    return run_zmarch<_Float16, 1, 64, 8, 2>(a, &b, 1, s, kInnerRanges);
 }
 
 // x slabs.  The end of row j-1 and the start of row j sit next to each

@@ -1,5 +1,6 @@
 """Helpers shared by the GPU tests (marshalling and comparisons only)."""
 import contextlib
+import os
 import sys
 
 import numpy as np
@@ -17,9 +18,25 @@ def say(*a):
 
 
 @contextlib.contextmanager
-def grid(n, periods=PER, overlaps=(2, 2, 2)):
+def grid(n, periods=PER, overlaps=(2, 2, 2), zmarch_min=0):
+    """The global grid for one test.  zmarch_min is the smallest region the
+    z-march kernels take (read at init): 0 sends every region through them,
+    as the large grids do, so small test grids exercise their tiling; None
+    keeps the library's default (small regions on the box kernels)."""
     nx, ny, nz = n
-    igg.init_global_grid(nx, ny, nz, dims=(1, 1, 1), periods=periods, overlaps=overlaps)
+    key = "IGG_ZMARCH_MIN_POINTS"
+    old = os.environ.get(key)
+    if zmarch_min is None:
+        os.environ.pop(key, None)
+    else:
+        os.environ[key] = str(zmarch_min)
+    try:
+        igg.init_global_grid(nx, ny, nz, dims=(1, 1, 1), periods=periods, overlaps=overlaps)
+    finally:
+        if old is None:
+            os.environ.pop(key, None)
+        else:
+            os.environ[key] = old
     try:
         yield
     finally:

@@ -67,6 +67,25 @@ def test_adjoint_multi_tile_matches_oracle(split):
     assert np.max(np.abs(inner(gC) - inner(gC_ref))) <= 1e-12 * np.max(np.abs(inner(gC_ref)))
 
 
+@pytest.mark.parametrize("n", [(40, 34, 30), (150, 60, 45)])
+def test_adjoint_box_kernel_and_zmarch_paths_equal(n):
+    """The adjoint's small-region box kernel and its z-march kernel give the
+    same bits."""
+    say("adjoint box vs zmarch", n)
+    nt = 5
+    T0, Ci, Tobs = _fields(n, 57)
+    dx = 1 / (n[0] - 1)
+    dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
+    res = []
+    for zmin in (None, 0):
+        with grid(n, zmarch_min=zmin):
+            prob = diffusion.Problem(1.0, dt, dx, dx, dx)
+            L, gT, gC, _ = diffusion.loss_and_grad(dev(T0), dev(Ci), dev(Tobs), prob, nt)
+            res.append((L, host(gT), host(gC)))
+    assert res[0][0] == res[1][0]
+    assert np.array_equal(res[0][1], res[1][1]) and np.array_equal(res[0][2], res[1][2])
+
+
 def test_autograd_function_matches_sweep():
     say("autograd")
     n = (36, 30, 28)

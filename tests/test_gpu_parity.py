@@ -156,6 +156,88 @@ def test_wide_rows_split_forms(n, dt_name):
         assert rel_max_err(outs[0], ref) <= 1e-12
 
 
+@pytest.mark.parametrize("n,ol,periods,splits", [
+    ((70, 30, 26), (3, 2, 2), (1, 1, 1), [None, (16, 4, 4), (3, 2, 2)]),
+    ((70, 30, 26), (4, 3, 2), (1, 0, 1), [None, (16, 4, 4), (5, 3, 2)]),
+    ((140, 24, 20), (3, 2, 3), (1, 1, 1), [None, (40, 3, 3), (64, 2, 3), (16, 2, 3)]),
+    ((66, 20, 18), (2, 2, 2), (0, 1, 1), [None, (16, 2, 2)]),
+])
+def test_wider_overlaps_match_oracle(n, ol, periods, splits):
+    """Overlaps above 2: the x halo of the result is the column ol-1 / nx-ol
+    copy, stored by the kernels that compute those columns, for every split
+    form (narrow, 64- and 128-point wrapped x slabs) and the unsplit step."""
+    nx, ny, nz = n
+    T0, Ci = synth.noisy_state_uniform_ci(nx, ny, nz, seed=23, noise=1e-2)
+    oracle.halo(T0, ol, periods)
+    oracle.halo(Ci, ol, periods)
+    dx = 1.0 / (nx - 1)
+    dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
+    ref = oracle.run(T0, Ci, 5, 1.0, dt, dx, dx, dx, ol=ol, periods=periods)
+    with grid(n, periods, ol):
+        T, C = dev(T0), dev(Ci)
+        for split in splits:
+            say("wider overlaps", n, ol, periods, split)
+            got = host(diffusion.forward(T.clone(), C, 5, 1.0, dt, dx, dx, dx, split=split))
+            # every point, halos included: the non-periodic halo planes keep T0's values
+            assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+            assert np.array_equal(got, oracle.halo(got.copy(), ol, periods))
+
+
+@pytest.mark.parametrize("dt_name", ["f64", "f32", "f16"])
+def test_schedules_and_x_exchange_forms_bit_exact(dt_name, monkeypatch):
+    """Every schedule (slabs and update on the helper stream beside the inner
+    region, slabs on the caller stream before it, or one chain on the caller
+    stream) and both x-exchange forms (fused into the
+    step kernels' stores with the x slabs in the inner launch, or a separate
+    x pass of the halo update with the x slabs in the boundary phase) give
+    the same bits, halos included, as the unsplit step."""
+    n = (96, 52, 41)
+    nx, ny, nz = n
+    T0, Ci = synth.noisy_state_uniform_ci(nx, ny, nz, seed=29, noise=1e-2)
+    oracle.halo(T0)
+    oracle.halo(Ci)
+    dx = 1.0 / (nx - 1)
+    dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
+    outs = []
+    for sched in ("1", "0", "2"):
+        for xform in ("fused", "halo"):
+            monkeypatch.setenv("IGG_SCHEDULE", sched)
+            monkeypatch.setenv("IGG_X_EXCHANGE", xform)
+            with grid(n):
+                T, C = dev(T0, DT[dt_name]), dev(Ci, DT[dt_name])
+                for split in [None, (16, 2, 2), (3, 4, 2)]:
+                    say("schedule", sched, "x exchange", xform, dt_name, split)
+                    o = diffusion.forward(T.clone(), C, 5, 1.0, dt, dx, dx, dx, split=split,
+                                          sr_seed=7 if dt_name == "f16" else None)
+                    outs.append(host(o))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("n", [(32, 32, 32), (96, 52, 41), (130, 70, 40), (33, 9, 11)])
+@pytest.mark.parametrize("dt_name", ["f64", "f32", "f16"])
+def test_box_kernel_and_zmarch_paths_bit_exact(n, dt_name):
+    """Small regions go to the one-thread-per-point box kernel by default;
+    forced through the z-march kernels they give the same bits."""
+    nx, ny, nz = n
+    T0, Ci = synth.noisy_state_uniform_ci(nx, ny, nz, seed=31, noise=1e-2)
+    oracle.halo(T0)
+    oracle.halo(Ci)
+    dx = 1.0 / (nx - 1)
+    dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
+    outs = []
+    for zmin in (None, 0):
+        with grid(n, zmarch_min=zmin):
+            T, C = dev(T0, DT[dt_name]), dev(Ci, DT[dt_name])
+            for split in [None, (16, 2, 2)]:
+                say("box vs zmarch", n, dt_name, zmin, split)
+                o = diffusion.forward(T.clone(), C, 4, 1.0, dt, dx, dx, dx, split=split,
+                                      sr_seed=7 if dt_name == "f16" else None)
+                outs.append(host(o))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
 @pytest.mark.parametrize("dt_name", ["f64", "f32", "f16"])
 def test_constant_state_exact_all_dtypes(dt_name):
     """Fig. 1's own state (T = 1.7, Ci = 1/c0) never changes, in any precision."""
