@@ -4,20 +4,25 @@ one MI355X.
 Workload (value): 512^3 FP64 local grid, 1x1x1 periodic topology, overlap 2,
 lam = 1, dx = 1/(n-1), T0 = 1.7 + Gaussian bump, Ci lognormal(log 0.5, 0.2)
 from seed 0, dt from maximum(Ci); every step is diffusion_step with
-boundary-first split (16, 2, 2): boundary slabs and the halo update
-(pack, exchange, unpack of T2) on the helper stream, the inner region on the
-caller stream.  A step = one such call; K steps are timed after W warm-up
-steps, with inputs already resident in HBM.
+boundary-first split (16, 2, 2): the y and z boundary slabs and the halo
+update of T2 (pack, exchange, unpack of the y and z planes) on the helper
+stream, the inner region and x slabs on the caller stream, the x exchange
+stored by the step kernels.  A step = one such call; K steps are timed after
+W warm-up steps, with inputs already resident in HBM.
 
 value = T_eff = (bytes of T read + Ci read + T2 written, each once per point)
 / time per step, in GB/s (decimal).
 
 Also reported on the same line:
   roofline      the inner-region step kernel: algorithmic bytes per launch
-                over its average duration, timed live with HIP events on the
-                stream it runs on, against the 8 TB/s HBM3E peak;
+                over its average duration, timed with HIP events on the
+                stream it runs on during a second pass of the same K steps,
+                against the 8 TB/s HBM3E peak;
+  ms_per_step_samples
+                20 more timings of K steps: median and its 95% interval;
   cpu_baseline  the CPU oracle on the host cores: 100 steps of the same
-                512^3 workload (bounded to about 10-30 s), as T_eff;
+                512^3 workload (bounded to about 10-30 s), as T_eff, and
+                one step on one core;
   variants      FP32 and FP16-storage steps at 512^3 (noisy-bump recipe,
                 uniform Ci) with their error against the FP64 result, the
                 unsplit FP64 step, and the checkpointed adjoint.
@@ -50,6 +55,8 @@ def parse():
     p.add_argument("--n", type=int, default=512, help="cube edge of the headline workload")
     p.add_argument("--no-variants", action="store_true", help="headline FP64 run only")
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    p.add_argument("--samples", type=int, default=20,
+                   help="extra timings of --steps steps for the median and its 95%% interval")
     p.add_argument("--profile", action="store_true",
                    help="headline loop only, for running under rocprofv3")
     p.add_argument("--split", default="16,2,2",
@@ -127,6 +134,41 @@ def time_steps(igg, torch, T, W, C, lam, dt, dx, dy, dz, steps, warmup, split, r
     return ms, final, per_launch, (k_points // max(1, k_launches)), b_ms / max(1, steps), ms_inst
 
 
+def step_samples(igg, torch, T, C, lam, dt, dx, dy, dz, steps, split, n):
+    """n more timings of `steps` steps each, continuing from T in fresh
+    buffers: median ms/step and the distribution-free 95% interval of the
+    median (order statistics; for n = 20 the 6th and 15th values)."""
+    if n < 1 or steps < 1:
+        return None
+    from math import comb
+    a, b = T.clone(), T.clone()
+    vals = []
+    for _ in range(n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            igg.diffusion_step(b, a, C, lam, dt, dx, dy, dz, split=split)
+            a, b = b, a
+        e1.record()
+        torch.cuda.synchronize()
+        vals.append(e0.elapsed_time(e1) / steps)
+    vals.sort()
+    med = vals[n // 2] if n % 2 else 0.5 * (vals[n // 2 - 1] + vals[n // 2])
+    # largest k with P(Binomial(n, 1/2) < k) <= 2.5%: [x_(k), x_(n+1-k)] covers the median with >= 95%
+    k, cdf = 0, 0.0
+    while k < n // 2:
+        p = comb(n, k) / 2.0 ** n
+        if cdf + p > 0.025:
+            break
+        cdf += p
+        k += 1
+    lo, hi = (vals[k - 1], vals[n - k]) if k >= 1 else (vals[0], vals[-1])
+    del a, b
+    return {"n": n, "steps_each": steps, "median": round(med, 5), "ci95": [round(lo, 5), round(hi, 5)],
+            "min": round(vals[0], 5), "max": round(vals[-1], 5)}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -159,6 +201,7 @@ def main():
     log(f"timing {K} FP64 steps after {Wm} warm-up steps, split {args.split}")
     split = None if args.split == "none" else tuple(int(v) for v in args.split.split(","))
     ms, out64, k_ms, k_pts, b_ms, ms_inst = time_steps(igg, torch, T, Wb, C, lam, dt, dx, dy, dz, K, Wm, split)
+    samples = step_samples(igg, torch, out64, C, lam, dt, dx, dy, dz, K, split, 0 if args.profile else args.samples)
     teff = 24.0 * pts / (ms * 1e-3) / 1e9
     k_bytes = 24.0 * k_pts
     k_gbs = k_bytes / (k_ms * 1e-3) / 1e9
@@ -182,6 +225,7 @@ def main():
                      "bytes_per_launch": k_bytes, "points_per_launch": k_pts,
                      "ms_per_launch": round(k_ms, 5), "kernel_source_hash": khash},
         "halo_overhead": None,
+        "ms_per_step_samples": samples,
         "boundary_ms_per_step": round(b_ms, 5),
         "ms_per_step_instrumented": round(ms_inst, 5),
     }
@@ -258,6 +302,17 @@ def main():
             err = oracle.rel_max_err(gpu64, cur)
             result["f64_err_vs_oracle"] = err
             log(f"FP64 GPU vs oracle after {done} steps: {err:.3e}")
+        # one step on one core, for the per-core figure
+        nthreads = oracle.num_threads()
+        oracle.set_num_threads(1)
+        t1 = time.perf_counter()
+        oracle.step(cur, Cih, lam, dt, dx, dy, dz, out=nxt)
+        oracle.halo(nxt)
+        one_core = time.perf_counter() - t1
+        oracle.set_num_threads(nthreads)
+        result["cpu_baseline"]["ms_per_step"] = round(el * 1e3 / done, 2)
+        result["cpu_baseline"]["ms_per_step_1_core"] = round(one_core * 1e3, 1)
+        log(f"oracle: {el * 1e3 / done:.1f} ms/step on {nthreads} threads, {one_core * 1e3:.1f} ms on one")
         del T0h, Cih, cur, nxt
 
     if args.no_variants:

@@ -27,7 +27,7 @@ template <typename C>
 __global__ void __launch_bounds__(256)
 k_adj_boxes(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restrict__ Tn,
             const C *__restrict__ Ci, C *__restrict__ gCi, BoxSet bs, int nx, int ny, C a, C rx, C ry,
-            C rz)
+            C rz, XHalo xh)
 {
     int i, j, k;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -43,6 +43,10 @@ k_adj_boxes(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restrict
     adjoint_point<C>(lp[p], lapmu, lapT, a, ln, g);
     lam_n[p] = ln;
     gCi[p] = g;
+    if (xh.on) {  // x exchange of lam_n with this process as its own neighbour
+        if (i == xh.lo) lam_n[p - i + nx - 1] = ln;
+        if (i == xh.hi) lam_n[p - i] = ln;
+    }
 }
 
 struct AdjTile {
@@ -52,6 +56,7 @@ struct AdjTile {
     int ntx, nty;
     int zc;
     int remap;
+    XHalo xh;
 };
 
 template <typename C, int VEC> struct AVec {
@@ -67,6 +72,16 @@ __device__ __forceinline__ C el(const typename AVec<C, VEC>::type &v, int q)
         return v;
     else
         return v[q];
+}
+// element q of a vector for a q known only at run time
+template <typename C, int VEC>
+__device__ __forceinline__ C el_dyn(const typename AVec<C, VEC>::type &v, int q)
+{
+    C x = el<C, VEC>(v, 0);
+#pragma unroll
+    for (int p = 1; p < VEC; ++p)
+        if (q == p) x = el<C, VEC>(v, p);
+    return x;
 }
 template <typename C, int VEC>
 __device__ __forceinline__ void set_el(typename AVec<C, VEC>::type &v, int q, C x)
@@ -241,6 +256,11 @@ k_adj_zmarch(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restric
                         gCi[p + q] = el<C, VEC>(go, q);
                     }
             }
+            // x exchange of lam_n with this process as its own neighbour
+            if (z.xh.on && xin && i <= z.xh.lo && i + VEC > z.xh.lo && z.xh.lo >= z.b.i0 && z.xh.lo < z.b.i1)
+                lam_n[p - i + nx - 1] = el_dyn<C, VEC>(lo, z.xh.lo - i);
+            if (z.xh.on && xin && i <= z.xh.hi && i + VEC > z.xh.hi && z.xh.hi >= z.b.i0 && z.xh.hi < z.b.i1)
+                lam_n[p - i] = el_dyn<C, VEC>(lo, z.xh.hi - i);
         }
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
@@ -275,7 +295,7 @@ static int run_boxes(const AdjArgs &a, const Box *b, int nb, hipStream_t s)
     if (threads == 0) return IGG_OK;
     hipLaunchKernelGGL(k_adj_boxes<C>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
                        (C *)a.lam_n, (const C *)a.lp, (const C *)a.Tn, (const C *)a.Ci, (C *)a.gCi, bs,
-                       a.nx, a.ny, (C)a.a, (C)a.rx, (C)a.ry, (C)a.rz);
+                       a.nx, a.ny, (C)a.a, (C)a.rx, (C)a.ry, (C)a.rz, a.xh);
     IGG_HIP(hipGetLastError());
     return IGG_OK;
 }
@@ -301,6 +321,7 @@ static int run_zmarch(const AdjArgs &a, const Box &b, hipStream_t s)
     if (zc < 1) zc = auto_zchunk((int64_t)z.ntx * z.nty, depth, 16);
     z.zc = zc;
     z.remap = env_int("IGG_ADJ_REMAP", 2);
+    z.xh = a.xh;
     int64_t blocks = (int64_t)z.ntx * z.nty * ((depth + zc - 1) / zc);
     if (blocks == 0) return IGG_OK;
     hipLaunchKernelGGL((k_adj_zmarch<C, VEC, BX, TY, RY>), dim3((unsigned)blocks), dim3(BX * TY), 0, s,

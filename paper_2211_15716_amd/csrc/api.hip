@@ -230,6 +230,70 @@ static int check_spacings(double lam, double dt, double dx, double dy, double dz
     return IGG_OK;
 }
 
+// One step with boundary-first split: the slabs the halo update reads, then
+// the update of `out`.  Schedule 1 runs both on the helper stream while the
+// inner region runs on the caller stream (as hide_communication does with
+// its boundary streams); schedule 0 runs the slabs on the caller stream ahead
+// of the inner region and only the update beside it; schedule 2 runs slabs,
+// update and inner region in that order on the caller stream.  By default
+// large inner regions take schedule 1; small grids are launch-bound, the
+// cross-stream fork and join cost more than the update they would hide, and
+// a captured graph of a single chain replays fastest, so they take schedule
+// 2.  When the x exchange is fused into the stores (or x is not periodic)
+// the update never reads the x slabs, so they join the inner launch and the
+// boundary phase is the y and z slabs.
+template <typename BoundaryLaunch, typename InnerLaunch>
+static int run_split(const int *split, const igg_field *out, int halo_dims, BoundaryLaunch boundary,
+                     InnerLaunch inner_launch, hipStream_t s)
+{
+    Grid &g = grid();
+    int rc;
+    Split sp;
+    plan_split(g.n, split, sp);
+    Split bnd = sp;
+    Box inner = sp.inner;
+    if (g.fuse_x) {
+        bnd.nb = 0;
+        for (int q = 0; q < sp.nb; ++q) {
+            if (sp.kind[q] == 0) continue;
+            bnd.boundary[bnd.nb] = sp.boundary[q];
+            bnd.kind[bnd.nb++] = sp.kind[q];
+        }
+        inner.i0 = 1;
+        inner.i1 = g.n[0] - 1;
+    }
+    const int sched = g.schedule >= 0 ? g.schedule : (box_points(inner) >= kSideMinPoints ? 1 : 2);
+    const bool on_side = sched == 1, serial = sched == 2;
+    hipStream_t bs = on_side ? g.side : s;
+    if (on_side) {
+        IGG_HIP(hipEventRecord(g.ev_fork, s));
+        IGG_HIP(hipStreamWaitEvent(g.side, g.ev_fork, 0));
+    }
+    if (bnd.nb) {
+        if ((rc = timing_mark(bs, 1))) return rc;
+        if ((rc = boundary(bnd, bs))) return rc;
+        if ((rc = timing_mark(bs, 1))) return rc;
+    }
+    if (serial) {
+        if ((rc = launch_halo(out, 1, s, halo_dims))) return rc;
+    } else {
+        if (!on_side) {
+            IGG_HIP(hipEventRecord(g.ev_fork, s));
+            IGG_HIP(hipStreamWaitEvent(g.side, g.ev_fork, 0));
+        }
+        if ((rc = launch_halo(out, 1, g.side, halo_dims))) return rc;
+        IGG_HIP(hipEventRecord(g.ev_join, g.side));
+    }
+    if (box_points(inner) > 0) {
+        if ((rc = timing_mark(s, 0))) return rc;
+        if ((rc = inner_launch(inner, s))) return rc;
+        if ((rc = timing_mark(s, 0))) return rc;
+        if (g.timing) { g.t_launches++; g.t_points += box_points(inner); }
+    }
+    if (!serial) IGG_HIP(hipStreamWaitEvent(s, g.ev_join, 0));
+    return IGG_OK;
+}
+
 }  // namespace igg
 
 using namespace igg;
@@ -404,63 +468,10 @@ int diffusion_step(const igg_field *T2, const igg_field *T, const igg_field *Ci,
         if (g.timing) { g.t_launches++; g.t_points += box_points(all); }
         return launch_halo(T2, 1, s, halo_dims);
     }
-    // Boundary first: the slabs the halo update reads, then the update of T2.
-    // Schedule 1 runs both on the helper stream while the inner region runs
-    // on the caller stream (as hide_communication does with its boundary
-    // streams); schedule 0 runs the slabs on the caller stream ahead of the
-    // inner region and only the update beside it; schedule 2 runs slabs,
-    // update and inner region in that order on the caller stream.  By
-    // default large inner regions take schedule 1; small grids are
-    // launch-bound, the cross-stream fork and join cost more than the update
-    // they would hide, and a captured graph of a single chain replays
-    // fastest, so they take schedule 2.  When the x exchange is fused into
-    // the stores (or x is not periodic) the update never reads the x slabs,
-    // so they join the inner launch and the boundary phase is the y and z
-    // slabs.
-    Split sp;
-    plan_split(g.n, split, sp);
-    Split bnd = sp;
-    Box inner = sp.inner;
-    if (g.fuse_x) {
-        bnd.nb = 0;
-        for (int q = 0; q < sp.nb; ++q) {
-            if (sp.kind[q] == 0) continue;
-            bnd.boundary[bnd.nb] = sp.boundary[q];
-            bnd.kind[bnd.nb++] = sp.kind[q];
-        }
-        inner.i0 = 1;
-        inner.i1 = g.n[0] - 1;
-    }
-    const int sched = g.schedule >= 0 ? g.schedule : (box_points(inner) >= kSideMinPoints ? 1 : 2);
-    const bool on_side = sched == 1, serial = sched == 2;
-    hipStream_t bs = on_side ? g.side : s;
-    if (on_side) {
-        IGG_HIP(hipEventRecord(g.ev_fork, s));
-        IGG_HIP(hipStreamWaitEvent(g.side, g.ev_fork, 0));
-    }
-    if (bnd.nb) {
-        if ((rc = timing_mark(bs, 1))) return rc;
-        if ((rc = launch_step_boundary(T->dtype, a, bnd, bs))) return rc;
-        if ((rc = timing_mark(bs, 1))) return rc;
-    }
-    if (serial) {
-        if ((rc = launch_halo(T2, 1, s, halo_dims))) return rc;
-    } else {
-        if (!on_side) {
-            IGG_HIP(hipEventRecord(g.ev_fork, s));
-            IGG_HIP(hipStreamWaitEvent(g.side, g.ev_fork, 0));
-        }
-        if ((rc = launch_halo(T2, 1, g.side, halo_dims))) return rc;
-        IGG_HIP(hipEventRecord(g.ev_join, g.side));
-    }
-    if (box_points(inner) > 0) {
-        if ((rc = timing_mark(s, 0))) return rc;
-        if ((rc = launch_step_inner(T->dtype, a, inner, s))) return rc;
-        if ((rc = timing_mark(s, 0))) return rc;
-        if (g.timing) { g.t_launches++; g.t_points += box_points(inner); }
-    }
-    if (!serial) IGG_HIP(hipStreamWaitEvent(s, g.ev_join, 0));
-    return IGG_OK;
+    return run_split(
+        split, T2, halo_dims,
+        [&](const Split &b, hipStream_t st) { return launch_step_boundary(T->dtype, a, b, st); },
+        [&](const Box &b, hipStream_t st) { return launch_step_inner(T->dtype, a, b, st); }, s);
 }
 
 int diffusion_dt(const igg_field *Ci, double lam, double dx, double dy, double dz, double *dt,
@@ -508,35 +519,23 @@ int diffusion_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1,
     if ((rc = ensure_device())) return rc;
 
     hipStream_t s = (hipStream_t)stream;
+    // the x exchange of lam_n is stored by the adjoint kernels, as in the step
+    const XHalo xh{(g.fuse_x && g.periods[0]) ? 1 : 0, g.ol[0] - 1, g.n[0] - g.ol[0]};
+    const int halo_dims = xh.on ? 6 : 7;
     AdjArgs a{lam_n->data, lam_np1->data, T_n->data, Ci->data, gCi->data, g.n[0], g.n[1], g.n[2],
-              dt * lam, 1.0 / (dx * dx), 1.0 / (dy * dy), 1.0 / (dz * dz)};
+              dt * lam, 1.0 / (dx * dx), 1.0 / (dy * dy), 1.0 / (dz * dz), xh};
     if (!split) {
         Box all{1, g.n[0] - 1, 1, g.n[1] - 1, 1, g.n[2] - 1};
         if ((rc = timing_mark(s, 0))) return rc;
         if ((rc = launch_adjoint_inner(dt_, a, all, s))) return rc;
         if ((rc = timing_mark(s, 0))) return rc;
         if (g.timing) { g.t_launches++; g.t_points += box_points(all); }
-        return launch_halo(lam_n, 1, s);
+        return launch_halo(lam_n, 1, s, halo_dims);
     }
-    Split sp;
-    plan_split(g.n, split, sp);
-    if (sp.nb) {
-        if ((rc = timing_mark(s, 1))) return rc;
-        if ((rc = launch_adjoint_boxes(dt_, a, sp.boundary, sp.nb, s))) return rc;
-        if ((rc = timing_mark(s, 1))) return rc;
-    }
-    IGG_HIP(hipEventRecord(g.ev_fork, s));
-    IGG_HIP(hipStreamWaitEvent(g.side, g.ev_fork, 0));
-    if ((rc = launch_halo(lam_n, 1, g.side))) return rc;
-    IGG_HIP(hipEventRecord(g.ev_join, g.side));
-    if (box_points(sp.inner) > 0) {
-        if ((rc = timing_mark(s, 0))) return rc;
-        if ((rc = launch_adjoint_inner(dt_, a, sp.inner, s))) return rc;
-        if ((rc = timing_mark(s, 0))) return rc;
-        if (g.timing) { g.t_launches++; g.t_points += box_points(sp.inner); }
-    }
-    IGG_HIP(hipStreamWaitEvent(s, g.ev_join, 0));
-    return IGG_OK;
+    return run_split(
+        split, lam_n, halo_dims,
+        [&](const Split &b, hipStream_t st) { return launch_adjoint_boxes(dt_, a, b.boundary, b.nb, st); },
+        [&](const Box &b, hipStream_t st) { return launch_adjoint_inner(dt_, a, b, st); }, s);
 }
 
 static int check_face(const igg_field *q, const char *name, int dim)

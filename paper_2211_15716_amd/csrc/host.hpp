@@ -134,6 +134,7 @@ struct AdjArgs {
     void *gCi;
     int nx, ny, nz;
     double a, rx, ry, rz;
+    XHalo xh;  // x exchange of lam_n fused into the stores
 };
 int launch_adjoint_boxes(int dtype, const AdjArgs &a, const Box *b, int nb, hipStream_t s);
 int launch_adjoint_inner(int dtype, const AdjArgs &a, const Box &b, hipStream_t s);
