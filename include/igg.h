@@ -69,6 +69,7 @@ extern "C" {
 #define IGG_RED_MAX_ABS 7      /* max |a| over inner points                     */
 
 #define IGG_MAX_FIELDS 8 /* fields per igg_update_halo call */
+#define IGG_MAX_RANKS 64 /* virtual ranks of one grid (product of dims) */
 
 /* A field: a device pointer, its element type and its size per dimension. */
 typedef struct igg_field {
@@ -93,11 +94,17 @@ typedef struct igg_rounding {
 
 /* Create the implicit global grid (Sec. 2; Fig. 1 `init_global_grid`).
  *   nx, ny, nz   local grid size; each must exceed the overlap (n >= ol+1).
- *   dims         processes per dimension, NULL or 0 = automatic; this library
- *                runs one process, so the product must be 1.
+ *   dims         ranks per dimension, NULL or 0 = 1.  A product P > 1 (at
+ *                most IGG_MAX_RANKS) makes this process hold all P ranks of
+ *                the Cartesian topology as separate local blocks on the
+ *                current device ("virtual ranks"; their exchange is a device
+ *                copy); the *_ranks entry points then take one field per
+ *                rank, and the single-block entry points return
+ *                IGG_ERR_STATE.
  *   periods      1 = periodic dimension, 0 = not; NULL = (0,0,0).
  *   overlaps     planes shared by neighbouring local grids, >= 2; NULL=(2,2,2).
- *   me           out, nullable: this process's rank (always 0).
+ *   me           out, nullable: this process's rank (always 0; virtual ranks
+ *                are addressed by index in the *_ranks calls).
  * Pure host work: no HIP call is made.
  * Errors: IGG_ERR_STATE if a grid exists, IGG_ERR_ARG for a bad value. */
 int igg_init_global_grid(int nx, int ny, int nz, const int dims[3], const int periods[3],
@@ -107,9 +114,29 @@ int igg_init_global_grid(int nx, int ny, int nz, const int dims[3], const int pe
  * n_g = dims*(n-ol) + ol*(1-period).  Errors: IGG_ERR_STATE, IGG_ERR_ARG. */
 int igg_global_size(int64_t n_g[3]);
 
-/* Grid description: any pointer may be NULL.  coords is the process's
- * Cartesian position (0,0,0).  Errors: IGG_ERR_STATE. */
+/* Grid description: any pointer may be NULL.  coords is rank 0's Cartesian
+ * position (0,0,0).  Errors: IGG_ERR_STATE. */
 int igg_topology(int n[3], int dims[3], int periods[3], int overlaps[3], int coords[3]);
+
+/* Number of ranks the grid holds (the product of dims; Sec. 2 `nprocs`).
+ * Errors: IGG_ERR_STATE, IGG_ERR_ARG (null). */
+int igg_nranks(int *nranks);
+
+/* Cartesian coordinates of rank `rank` (Sec. 2 `coords`): rank r sits at
+ * (r % dims[0], (r / dims[0]) % dims[1], r / (dims[0]*dims[1])), x fastest.
+ * Its block holds the points c*(n-ol) + l, l = 0..n-1, of a global index
+ * space 0 .. dims*(n-ol)+ol-1 per dimension (one block of that size is the
+ * same grid; in a periodic dimension its first and last ol planes are
+ * images of each other).
+ * Errors: IGG_ERR_STATE, IGG_ERR_ARG (null, rank outside 0..P-1). */
+int igg_rank_coords(int rank, int coords[3]);
+
+/* Neighbours of rank `rank` per dimension (Sec. 2 `neighbors`): lower[d] and
+ * upper[d] are the ranks one step down and up in dimension d, wrapping in a
+ * periodic dimension, -1 at the edge of a non-periodic one (a periodic
+ * dimension with dims 1 is its own neighbour).
+ * Errors: IGG_ERR_STATE, IGG_ERR_ARG. */
+int igg_neighbors(int rank, int lower[3], int upper[3]);
 
 /* Halo update of up to IGG_MAX_FIELDS fields (Fig. 1 `update_halo!`, Sec. 2).
  * For each dimension in the order x, y, z, and each periodic one: pack the
@@ -128,6 +155,16 @@ int igg_topology(int n[3], int dims[3], int periods[3], int overlaps[3], int coo
  * the same data pointer), IGG_ERR_HIP. */
 int igg_update_halo(const igg_field *fields, int nfields, void *stream);
 
+/* igg_update_halo for every rank of the grid: fields[r*nfields + f] is field
+ * f of rank r (nfields fields per rank, all of one field index f alike in
+ * size and dtype).  Per dimension, in the order x, y, z: each rank packs its
+ * planes ol_A-1 and n_A-ol_A into its send buffers, which are copied into
+ * the receive buffers of its lower and upper neighbours, and unpacked into
+ * their planes n_A-1 and 0; with one rank this is igg_update_halo.
+ * Errors: as igg_update_halo; IGG_ERR_SIZE if a field differs in size or
+ * dtype from the same field of rank 0. */
+int igg_update_halo_ranks(const igg_field *fields, int nfields, void *stream);
+
 /* Finalize the grid (Fig. 1 `finalize_global_grid`): wait for the library's
  * stream, free buffers, stream and events, forget the grid.
  * Errors: IGG_ERR_STATE if no grid exists, IGG_ERR_HIP. */
@@ -143,9 +180,13 @@ int igg_finalize_global_grid(void);
  * element type; T must carry a valid halo (the previous step's update).
  *   split  boundary widths (Fig. 1 `@hide_communication (16, 2, 2)`), counted
  *          from the array edge including the halo plane, each >= overlap.
- *          The boundary slabs are computed first on `stream`; then the halo
- *          update of T2 runs on the library's helper stream while the inner
- *          region runs on `stream`, which finally waits for the helper.
+ *          The boundary slabs the halo update reads are computed first and
+ *          the update of T2 follows them on the library's helper stream,
+ *          while the inner region runs on `stream`, which finally waits for
+ *          the helper.  The x exchange is stored by the step kernels as they
+ *          compute the points it moves, so the x slabs are computed with the
+ *          inner region.  Inner regions below 2^21 points run slabs, update
+ *          and inner region as one chain on `stream` (launch-bound sizes).
  *          NULL = no overlap: everything runs on `stream` in order.
  *   rnd    FP16 store rounding, NULL = round to nearest even (ignored for
  *          FP64/FP32).
@@ -156,6 +197,18 @@ int igg_finalize_global_grid(void);
 int diffusion_step(const igg_field *T2, const igg_field *T, const igg_field *Ci, double lam,
                    double dt, double dx, double dy, double dz, const int split[3],
                    const igg_rounding *rnd, void *stream);
+
+/* diffusion_step for every rank of the grid: T2[r], T[r] and Ci[r] are rank
+ * r's blocks (arrays of nranks fields, no block sharing memory with
+ * another).  The step runs on each block, the x exchange stores into the x
+ * neighbours' blocks, and one igg_update_halo_ranks of T2 follows, with the
+ * same split schedule as diffusion_step.  FP16 stochastic rounding hashes
+ * each point's global index, so the result equals the single-block run of
+ * the global grid bit for bit.
+ * Errors: as diffusion_step, naming the rank. */
+int diffusion_step_ranks(const igg_field *T2, const igg_field *T, const igg_field *Ci, double lam,
+                         double dt, double dx, double dy, double dz, const int split[3],
+                         const igg_rounding *rnd, void *stream);
 
 /* Stable time step of Fig. 1: dt = min(dx^2,dy^2,dz^2)/lam/maximum(Ci)/6.1,
  * the maximum taken in FP64 over every point of Ci on the GPU.

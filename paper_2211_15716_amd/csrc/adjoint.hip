@@ -43,10 +43,9 @@ k_adj_boxes(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restrict
     adjoint_point<C>(lp[p], lapmu, lapT, a, ln, g);
     lam_n[p] = ln;
     gCi[p] = g;
-    if (xh.on) {  // x exchange of lam_n with this process as its own neighbour
-        if (i == xh.lo) lam_n[p - i + nx - 1] = ln;
-        if (i == xh.hi) lam_n[p - i] = ln;
-    }
+    // x exchange of lam_n fused into the store
+    if (xh.on_lo && i == xh.lo) lam_n[p - i + nx - 1 + xh.d_lo] = ln;
+    if (xh.on_hi && i == xh.hi) lam_n[p - i + xh.d_hi] = ln;
 }
 
 struct AdjTile {
@@ -256,11 +255,11 @@ k_adj_zmarch(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restric
                         gCi[p + q] = el<C, VEC>(go, q);
                     }
             }
-            // x exchange of lam_n with this process as its own neighbour
-            if (z.xh.on && xin && i <= z.xh.lo && i + VEC > z.xh.lo && z.xh.lo >= z.b.i0 && z.xh.lo < z.b.i1)
-                lam_n[p - i + nx - 1] = el_dyn<C, VEC>(lo, z.xh.lo - i);
-            if (z.xh.on && xin && i <= z.xh.hi && i + VEC > z.xh.hi && z.xh.hi >= z.b.i0 && z.xh.hi < z.b.i1)
-                lam_n[p - i] = el_dyn<C, VEC>(lo, z.xh.hi - i);
+            // x exchange of lam_n fused into the store
+            if (z.xh.on_lo && xin && i <= z.xh.lo && i + VEC > z.xh.lo && z.xh.lo >= z.b.i0 && z.xh.lo < z.b.i1)
+                lam_n[p - i + nx - 1 + z.xh.d_lo] = el_dyn<C, VEC>(lo, z.xh.lo - i);
+            if (z.xh.on_hi && xin && i <= z.xh.hi && i + VEC > z.xh.hi && z.xh.hi >= z.b.i0 && z.xh.hi < z.b.i1)
+                lam_n[p - i + z.xh.d_hi] = el_dyn<C, VEC>(lo, z.xh.hi - i);
         }
 #pragma unroll
         for (int r = 0; r < RY; ++r) {

@@ -36,6 +36,27 @@ Grid &grid()
 
 int64_t zmarch_min_points() { return grid().zmarch_min; }
 
+void rank_coords(int r, int c[3])
+{
+    const Grid &g = grid();
+    c[0] = r % g.dims[0];
+    c[1] = (r / g.dims[0]) % g.dims[1];
+    c[2] = r / (g.dims[0] * g.dims[1]);
+}
+
+int rank_neighbor(int r, int d, int side)
+{
+    const Grid &g = grid();
+    int c[3];
+    rank_coords(r, c);
+    c[d] += side ? 1 : -1;
+    if (c[d] < 0 || c[d] >= g.dims[d]) {
+        if (!g.periods[d]) return -1;
+        c[d] = (c[d] + g.dims[d]) % g.dims[d];
+    }
+    return c[0] + g.dims[0] * (c[1] + g.dims[1] * c[2]);
+}
+
 int elem_bytes(int dtype) { return dtype == IGG_F64 ? 8 : dtype == IGG_F32 ? 4 : 2; }
 
 int64_t field_elems(const igg_field &f) { return f.size[0] * f.size[1] * f.size[2]; }
@@ -150,7 +171,7 @@ int ensure_device()
             m2 = (int64_t)(g.n[0] + 1) * (g.n[1] + 1);
     int64_t cap = std::max(m0, std::max(m1, m2)) * 8;
     g.halo_cap = (size_t)((cap + 255) / 256 * 256);
-    IGG_HIP(hipMalloc((void **)&g.halo_buf, g.halo_cap * 2 * 2 * IGG_MAX_FIELDS));
+    IGG_HIP(hipMalloc((void **)&g.halo_buf, g.halo_cap * 2 * 2 * IGG_MAX_FIELDS * g.nranks));
     IGG_HIP(hipMalloc((void **)&g.red_part, 8192 * sizeof(double)));
     IGG_HIP(hipHostMalloc((void **)&g.red_host, 64 * sizeof(double), hipHostMallocDefault));
     g.device = dev;
@@ -242,6 +263,8 @@ static int check_spacings(double lam, double dt, double dx, double dy, double dz
 // 2.  When the x exchange is fused into the stores (or x is not periodic)
 // the update never reads the x slabs, so they join the inner launch and the
 // boundary phase is the y and z slabs.
+// boundary(r, slabs, stream) and inner(r, box, stream) launch rank r's
+// kernels; out holds the updated field of every rank.
 template <typename BoundaryLaunch, typename InnerLaunch>
 static int run_split(const int *split, const igg_field *out, int halo_dims, BoundaryLaunch boundary,
                      InnerLaunch inner_launch, hipStream_t s)
@@ -271,7 +294,8 @@ static int run_split(const int *split, const igg_field *out, int halo_dims, Boun
     }
     if (bnd.nb) {
         if ((rc = timing_mark(bs, 1))) return rc;
-        if ((rc = boundary(bnd, bs))) return rc;
+        for (int r = 0; r < g.nranks; ++r)
+            if ((rc = boundary(r, bnd, bs))) return rc;
         if ((rc = timing_mark(bs, 1))) return rc;
     }
     if (serial) {
@@ -284,14 +308,129 @@ static int run_split(const int *split, const igg_field *out, int halo_dims, Boun
         if ((rc = launch_halo(out, 1, g.side, halo_dims))) return rc;
         IGG_HIP(hipEventRecord(g.ev_join, g.side));
     }
-    if (box_points(inner) > 0) {
+    for (int r = 0; r < g.nranks && box_points(inner) > 0; ++r) {
         if ((rc = timing_mark(s, 0))) return rc;
-        if ((rc = inner_launch(inner, s))) return rc;
+        if ((rc = inner_launch(r, inner, s))) return rc;
         if ((rc = timing_mark(s, 0))) return rc;
         if (g.timing) { g.t_launches++; g.t_points += box_points(inner); }
     }
     if (!serial) IGG_HIP(hipStreamWaitEvent(s, g.ev_join, 0));
     return IGG_OK;
+}
+
+// The step's launch arguments for rank r: its arrays, the fused x exchange
+// into its x neighbours' arrays, and its origin in the global index space.
+static int step_args(int r, const igg_field *T2, const igg_field *T, const igg_field *Ci, double lam,
+                     double dt, double dx, double dy, double dz, uint32_t key, int stochastic, StepArgs &a)
+{
+    Grid &g = grid();
+    int c[3];
+    rank_coords(r, c);
+    XHalo xh{0, 0, g.ol[0] - 1, g.n[0] - g.ol[0], 0, 0};
+    if (g.fuse_x) {
+        const int64_t esz = elem_bytes(T2[r].dtype);
+        for (int side = 0; side < 2; ++side) {
+            const int q = rank_neighbor(r, 0, side);
+            if (q < 0) continue;
+            const int64_t diff = (int64_t)((intptr_t)T2[q].data - (intptr_t)T2[r].data);
+            if (diff % esz) return fail(IGG_ERR_ARG, "T2 blocks must be aligned to their element size");
+            (side == 0 ? xh.on_lo : xh.on_hi) = 1;
+            (side == 0 ? xh.d_lo : xh.d_hi) = diff / esz;
+        }
+    }
+    const SrOrigin so{c[0] * (g.n[0] - g.ol[0]), c[1] * (g.n[1] - g.ol[1]), c[2] * (g.n[2] - g.ol[2]),
+                      g.dims[0] * (g.n[0] - g.ol[0]) + g.ol[0]};
+    a = StepArgs{T2[r].data, T[r].data, Ci[r].data, g.n[0], g.n[1], g.n[2],
+                 dt * lam, 1.0 / (dx * dx), 1.0 / (dy * dy), 1.0 / (dz * dz), key, stochastic, xh, so};
+    return IGG_OK;
+}
+
+// diffusion_step for the grid's nranks ranks: fields[r] is rank r's block.
+static int step_ranks(const igg_field *T2, const igg_field *T, const igg_field *Ci, double lam, double dt,
+                      double dx, double dy, double dz, const int split[3], const igg_rounding *rnd,
+                      void *stream)
+{
+    Grid &g = grid();
+    int rc;
+    const int P = g.nranks;
+    for (int r = 0; r < P; ++r) {
+        const std::string sfx = P > 1 ? "[" + std::to_string(r) + "]" : "";
+        if ((rc = check_field(&T2[r], ("T2" + sfx).c_str(), true))) return rc;
+        if ((rc = check_field(&T[r], ("T" + sfx).c_str(), true))) return rc;
+        if ((rc = check_field(&Ci[r], ("Ci" + sfx).c_str(), true))) return rc;
+        if (T2[r].dtype != T[0].dtype || T[r].dtype != T[0].dtype || Ci[r].dtype != T[0].dtype)
+            return fail(IGG_ERR_DTYPE, "T2, T and Ci must share one dtype");
+    }
+    for (int r = 0; r < P; ++r)
+        for (int q = 0; q < P; ++q) {
+            if (overlaps_mem(T2[r], T[q]) || overlaps_mem(T2[r], Ci[q]))
+                return fail(IGG_ERR_ALIAS, "T2 shares memory with T or Ci");
+            if (q != r && overlaps_mem(T2[r], T2[q])) return fail(IGG_ERR_ALIAS, "two T2 blocks share memory");
+        }
+    if ((rc = check_spacings(lam, dt, dx, dy, dz))) return rc;
+    if ((rc = check_split(split, g.ol))) return rc;
+    int stochastic = 0;
+    uint32_t key = 0;
+    if (rnd) {
+        if (rnd->reserved != 0) return fail(IGG_ERR_ARG, "rounding.reserved must be 0");
+        if (rnd->mode != IGG_ROUND_NEAREST && rnd->mode != IGG_ROUND_STOCHASTIC)
+            return fail(IGG_ERR_ARG, "unknown rounding mode");
+        stochastic = rnd->mode == IGG_ROUND_STOCHASTIC;
+        key = sr_key(rnd->seed, rnd->counter);
+    }
+    std::vector<StepArgs> args(P);
+    for (int r = 0; r < P; ++r)
+        if ((rc = step_args(r, T2, T, Ci, lam, dt, dx, dy, dz, key, stochastic, args[r]))) return rc;
+    if ((rc = ensure_device())) return rc;
+
+    // With x periodic the step kernels also store the x halo of T2 (the
+    // exchange between x neighbours on this device is a copy of the two
+    // source columns, fused into the kernels that compute them); the halo
+    // update then moves the y and z planes only.
+    const int halo_dims = g.fuse_x ? 6 : 7;
+    const int dtype = T[0].dtype;
+    hipStream_t s = (hipStream_t)stream;
+    if (!split) {
+        Box all{1, g.n[0] - 1, 1, g.n[1] - 1, 1, g.n[2] - 1};
+        for (int r = 0; r < P; ++r) {
+            if ((rc = timing_mark(s, 0))) return rc;
+            if ((rc = launch_step_inner(dtype, args[r], all, s))) return rc;
+            if ((rc = timing_mark(s, 0))) return rc;
+            if (g.timing) { g.t_launches++; g.t_points += box_points(all); }
+        }
+        return launch_halo(T2, 1, s, halo_dims);
+    }
+    return run_split(
+        split, T2, halo_dims,
+        [&](int r, const Split &b, hipStream_t st) { return launch_step_boundary(dtype, args[r], b, st); },
+        [&](int r, const Box &b, hipStream_t st) { return launch_step_inner(dtype, args[r], b, st); }, s);
+}
+
+// update_halo over the grid's ranks: fields[r * nfields + f] is field f of
+// rank r; field f has one size and dtype on every rank.
+static int update_halo_ranks(const igg_field *fields, int nfields, void *stream)
+{
+    Grid &g = grid();
+    if (!fields) return fail(IGG_ERR_ARG, "fields is null");
+    if (nfields < 1 || nfields > IGG_MAX_FIELDS)
+        return fail(IGG_ERR_ARG, "nfields must be in 1.." + std::to_string(IGG_MAX_FIELDS));
+    int rc;
+    const int total = nfields * g.nranks;
+    for (int e = 0; e < total; ++e) {
+        const int r = e / nfields, f = e % nfields;
+        std::string nm = "field " + std::to_string(f) + (g.nranks > 1 ? " of rank " + std::to_string(r) : "");
+        if ((rc = check_field(&fields[e], nm.c_str(), false))) return rc;
+        const igg_field &f0 = fields[f];
+        if (fields[e].dtype != f0.dtype || fields[e].size[0] != f0.size[0] || fields[e].size[1] != f0.size[1] ||
+            fields[e].size[2] != f0.size[2])
+            return fail(IGG_ERR_SIZE, nm + " differs in size or dtype from the same field of rank 0");
+        for (int q = 0; q < e; ++q)
+            if (overlaps_mem(fields[e], fields[q]))
+                return fail(IGG_ERR_ALIAS, "fields " + std::to_string(q) + " and " + std::to_string(e) +
+                                               " share memory");
+    }
+    if ((rc = ensure_device())) return rc;
+    return launch_halo(fields, nfields, (hipStream_t)stream);
 }
 
 }  // namespace igg
@@ -323,8 +462,9 @@ int igg_init_global_grid(int nx, int ny, int nz, const int dims[3], const int pe
                                          " must exceed the overlap " + std::to_string(ol[d]));
         if (n[d] > (1 << 24)) return fail(IGG_ERR_ARG, "local size above 2^24");
     }
-    if ((int64_t)dm[0] * dm[1] * dm[2] != 1)
-        return fail(IGG_ERR_ARG, "dims must multiply to the number of processes, which is 1");
+    const int64_t P = (int64_t)dm[0] * dm[1] * dm[2];
+    if (P < 1 || P > IGG_MAX_RANKS)
+        return fail(IGG_ERR_ARG, "dims must multiply to a rank count in 1.." + std::to_string(IGG_MAX_RANKS));
     if ((int64_t)(nx + 1) * (ny + 1) > 0x7fffffffLL || (int64_t)(nx + 1) * (nz + 1) > 0x7fffffffLL ||
         (int64_t)(ny + 1) * (nz + 1) > 0x7fffffffLL)
         return fail(IGG_ERR_ARG, "a plane of the grid exceeds 2^31 points");
@@ -334,6 +474,7 @@ int igg_init_global_grid(int nx, int ny, int nz, const int dims[3], const int pe
         g.periods[d] = per[d];
         g.dims[d] = dm[d];
     }
+    g.nranks = (int)P;
     g.init = true;
     g.timing = false;
     {
@@ -378,21 +519,49 @@ int igg_update_halo(const igg_field *fields, int nfields, void *stream)
 {
     Grid &g = grid();
     if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
-    if (!fields) return fail(IGG_ERR_ARG, "fields is null");
-    if (nfields < 1 || nfields > IGG_MAX_FIELDS)
-        return fail(IGG_ERR_ARG, "nfields must be in 1.." + std::to_string(IGG_MAX_FIELDS));
-    int rc;
-    for (int f = 0; f < nfields; ++f) {
-        std::string nm = "field " + std::to_string(f);
-        if ((rc = check_field(&fields[f], nm.c_str(), false))) return rc;
-        for (int q = 0; q < f; ++q)
-            if (overlaps_mem(fields[f], fields[q]))
-                return fail(IGG_ERR_ALIAS, "fields " + std::to_string(q) + " and " + std::to_string(f) +
-                                               " share memory");
-    }
-    if ((rc = ensure_device())) return rc;
-    return launch_halo(fields, nfields, (hipStream_t)stream);
+    if (g.nranks > 1) return fail(IGG_ERR_STATE, "the grid holds several virtual ranks: use igg_update_halo_ranks");
+    return update_halo_ranks(fields, nfields, stream);
 }
+
+int igg_update_halo_ranks(const igg_field *fields, int nfields, void *stream)
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    return update_halo_ranks(fields, nfields, stream);
+}
+
+int igg_nranks(int *nranks)
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    if (!nranks) return fail(IGG_ERR_ARG, "nranks is null");
+    *nranks = g.nranks;
+    return IGG_OK;
+}
+
+int igg_rank_coords(int rank, int coords[3])
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    if (!coords) return fail(IGG_ERR_ARG, "coords is null");
+    if (rank < 0 || rank >= g.nranks) return fail(IGG_ERR_ARG, "rank out of range");
+    rank_coords(rank, coords);
+    return IGG_OK;
+}
+
+int igg_neighbors(int rank, int lower[3], int upper[3])
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    if (!lower || !upper) return fail(IGG_ERR_ARG, "null argument");
+    if (rank < 0 || rank >= g.nranks) return fail(IGG_ERR_ARG, "rank out of range");
+    for (int d = 0; d < 3; ++d) {
+        lower[d] = rank_neighbor(rank, d, 0);
+        upper[d] = rank_neighbor(rank, d, 1);
+    }
+    return IGG_OK;
+}
+
 
 int igg_finalize_global_grid(void)
 {
@@ -430,48 +599,19 @@ int diffusion_step(const igg_field *T2, const igg_field *T, const igg_field *Ci,
 {
     Grid &g = grid();
     if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
-    int rc;
-    if ((rc = check_field(T2, "T2", true))) return rc;
-    if ((rc = check_field(T, "T", true))) return rc;
-    if ((rc = check_field(Ci, "Ci", true))) return rc;
-    if (T2->dtype != T->dtype || Ci->dtype != T->dtype)
-        return fail(IGG_ERR_DTYPE, "T2, T and Ci must share one dtype");
-    if (overlaps_mem(*T2, *T) || overlaps_mem(*T2, *Ci))
-        return fail(IGG_ERR_ALIAS, "T2 shares memory with T or Ci");
-    if ((rc = check_spacings(lam, dt, dx, dy, dz))) return rc;
-    if ((rc = check_split(split, g.ol))) return rc;
-    int stochastic = 0;
-    uint32_t key = 0;
-    if (rnd) {
-        if (rnd->reserved != 0) return fail(IGG_ERR_ARG, "rounding.reserved must be 0");
-        if (rnd->mode != IGG_ROUND_NEAREST && rnd->mode != IGG_ROUND_STOCHASTIC)
-            return fail(IGG_ERR_ARG, "unknown rounding mode");
-        stochastic = rnd->mode == IGG_ROUND_STOCHASTIC;
-        key = sr_key(rnd->seed, rnd->counter);
-    }
-    if ((rc = ensure_device())) return rc;
+    if (g.nranks > 1) return fail(IGG_ERR_STATE, "the grid holds several virtual ranks: use diffusion_step_ranks");
+    if (!T2 || !T || !Ci) return fail(IGG_ERR_ARG, "null field");
+    return step_ranks(T2, T, Ci, lam, dt, dx, dy, dz, split, rnd, stream);
+}
 
-    hipStream_t s = (hipStream_t)stream;
-    // With x periodic the step kernels also store the x halo of T2 (the
-    // exchange with this process as its own neighbour is a copy of the two
-    // source columns, fused into the kernels that compute them); the halo
-    // update then moves the y and z planes only.
-    const XHalo xh{(g.fuse_x && g.periods[0]) ? 1 : 0, g.ol[0] - 1, g.n[0] - g.ol[0]};
-    const int halo_dims = xh.on ? 6 : 7;
-    StepArgs a{T2->data, T->data, Ci->data, g.n[0], g.n[1], g.n[2],
-               dt * lam, 1.0 / (dx * dx), 1.0 / (dy * dy), 1.0 / (dz * dz), key, stochastic, xh};
-    if (!split) {
-        Box all{1, g.n[0] - 1, 1, g.n[1] - 1, 1, g.n[2] - 1};
-        if ((rc = timing_mark(s, 0))) return rc;
-        if ((rc = launch_step_inner(T->dtype, a, all, s))) return rc;
-        if ((rc = timing_mark(s, 0))) return rc;
-        if (g.timing) { g.t_launches++; g.t_points += box_points(all); }
-        return launch_halo(T2, 1, s, halo_dims);
-    }
-    return run_split(
-        split, T2, halo_dims,
-        [&](const Split &b, hipStream_t st) { return launch_step_boundary(T->dtype, a, b, st); },
-        [&](const Box &b, hipStream_t st) { return launch_step_inner(T->dtype, a, b, st); }, s);
+int diffusion_step_ranks(const igg_field *T2, const igg_field *T, const igg_field *Ci, double lam,
+                         double dt, double dx, double dy, double dz, const int split[3],
+                         const igg_rounding *rnd, void *stream)
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    if (!T2 || !T || !Ci) return fail(IGG_ERR_ARG, "null field array");
+    return step_ranks(T2, T, Ci, lam, dt, dx, dy, dz, split, rnd, stream);
 }
 
 int diffusion_dt(const igg_field *Ci, double lam, double dx, double dy, double dz, double *dt,
@@ -499,6 +639,7 @@ int diffusion_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1,
 {
     Grid &g = grid();
     if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    if (g.nranks > 1) return fail(IGG_ERR_STATE, "this entry point runs on a single-rank grid");
     int rc;
     if ((rc = check_field(lam_n, "lam_n", true))) return rc;
     if ((rc = check_field(lam_np1, "lam_np1", true))) return rc;
@@ -520,8 +661,9 @@ int diffusion_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1,
 
     hipStream_t s = (hipStream_t)stream;
     // the x exchange of lam_n is stored by the adjoint kernels, as in the step
-    const XHalo xh{(g.fuse_x && g.periods[0]) ? 1 : 0, g.ol[0] - 1, g.n[0] - g.ol[0]};
-    const int halo_dims = xh.on ? 6 : 7;
+    const int xon = (g.fuse_x && g.periods[0]) ? 1 : 0;
+    const XHalo xh{xon, xon, g.ol[0] - 1, g.n[0] - g.ol[0], 0, 0};
+    const int halo_dims = g.fuse_x ? 6 : 7;
     AdjArgs a{lam_n->data, lam_np1->data, T_n->data, Ci->data, gCi->data, g.n[0], g.n[1], g.n[2],
               dt * lam, 1.0 / (dx * dx), 1.0 / (dy * dy), 1.0 / (dz * dz), xh};
     if (!split) {
@@ -534,8 +676,8 @@ int diffusion_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1,
     }
     return run_split(
         split, lam_n, halo_dims,
-        [&](const Split &b, hipStream_t st) { return launch_adjoint_boxes(dt_, a, b.boundary, b.nb, st); },
-        [&](const Box &b, hipStream_t st) { return launch_adjoint_inner(dt_, a, b, st); }, s);
+        [&](int, const Split &b, hipStream_t st) { return launch_adjoint_boxes(dt_, a, b.boundary, b.nb, st); },
+        [&](int, const Box &b, hipStream_t st) { return launch_adjoint_inner(dt_, a, b, st); }, s);
 }
 
 static int check_face(const igg_field *q, const char *name, int dim)
@@ -556,6 +698,7 @@ int diffusion_flux_step(const igg_field *T2, const igg_field *T, const igg_field
 {
     Grid &g = grid();
     if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    if (g.nranks > 1) return fail(IGG_ERR_STATE, "this entry point runs on a single-rank grid");
     int rc;
     if ((rc = check_field(T2, "T2", true))) return rc;
     if ((rc = check_field(T, "T", true))) return rc;
@@ -596,6 +739,7 @@ int diffusion_flux_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1
 {
     Grid &g = grid();
     if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    if (g.nranks > 1) return fail(IGG_ERR_STATE, "this entry point runs on a single-rank grid");
     int rc;
     if ((rc = check_field(lam_n, "lam_n", true))) return rc;
     if ((rc = check_field(lam_np1, "lam_np1", true))) return rc;

@@ -9,21 +9,24 @@
 // the halo values an earlier one wrote, and edges and corners come out as
 // images in every periodic dimension.
 //
-// On this single-process grid a periodic dimension is its own neighbour on
-// both sides, so the exchange is a device copy between the library's send
-// and receive buffers, and one launch per dimension runs all three phases:
-// each thread packs its elements, exchanges them and unpacks them.
+// The process holds every rank of the topology (one, or several virtual
+// ranks as separate blocks on this device), so the exchange is a device copy
+// from a rank's send buffer into its neighbour's receive buffer; a periodic
+// dimension of one rank is its own neighbour on both sides.  One launch per
+// dimension and rank runs all three phases: each thread packs its elements,
+// exchanges them and unpacks them into the neighbour's halo.
 #include "host.hpp"
 
 namespace igg {
 
-// One side of one field in one dimension.  Element (a, b) of the plane is
-// at base[plane*sd + a*sa + b*sb] and at buf[a + na*b]; units are `esz`
-// bytes (16 when whole rows move as 16-byte vectors).
+// One side of one field in one dimension.  Element (a, b) of a plane is at
+// base[plane*sd + a*sa + b*sb] and at buf[a + na*b]; units are `esz` bytes
+// (16 when whole rows move as 16-byte vectors).
 struct HaloDesc {
-    unsigned char *base;
-    unsigned char *send;  // my send buffer for this side
-    unsigned char *recv;  // the receive buffer this side's data lands in
+    unsigned char *src_base;  // my field
+    unsigned char *dst_base;  // the neighbour's field (mine on a periodic single rank)
+    unsigned char *send;      // my send buffer for this side
+    unsigned char *recv;      // the neighbour's receive buffer this side's data lands in
     int64_t sd, sa, sb;
     int na, nb;
     int src, dst;  // plane packed from, plane unpacked into
@@ -40,12 +43,13 @@ __device__ __forceinline__ void halo_elem(const HaloDesc &d, int64_t e)
     const int a = (int)(e % d.na);
     const int b = (int)(e / d.na);
     const int64_t off = (int64_t)a * d.sa + (int64_t)b * d.sb;
-    E *A = reinterpret_cast<E *>(d.base);
+    const E *A = reinterpret_cast<const E *>(d.src_base);
+    E *B = reinterpret_cast<E *>(d.dst_base);
     E *send = reinterpret_cast<E *>(d.send);
     E *recv = reinterpret_cast<E *>(d.recv);
     send[e] = A[(int64_t)d.src * d.sd + off];  // pack
-    recv[e] = send[e];                         // exchange with the neighbour (this process)
-    A[(int64_t)d.dst * d.sd + off] = recv[e];  // unpack
+    recv[e] = send[e];                         // exchange (a device copy: the neighbour is on this GPU)
+    B[(int64_t)d.dst * d.sd + off] = recv[e];  // unpack into the neighbour's halo
 }
 
 // blockIdx.y selects the (field, side); x-threads walk the plane.
@@ -64,65 +68,83 @@ __global__ void __launch_bounds__(256) k_halo_self(HaloSet hs)
     }
 }
 
-static unsigned char *send_buf(Grid &g, int f, int side)
+// Rank r owns 4 * IGG_MAX_FIELDS planes: send buffers of (field, side), then
+// receive buffers of (field, side); side 0 faces the lower neighbour.
+static unsigned char *send_buf(Grid &g, int r, int f, int side)
 {
-    return g.halo_buf + (size_t)(f * 2 + side) * g.halo_cap;
+    return g.halo_buf + ((size_t)r * 4 * IGG_MAX_FIELDS + f * 2 + side) * g.halo_cap;
 }
 
-static unsigned char *recv_buf(Grid &g, int f, int side)
+static unsigned char *recv_buf(Grid &g, int r, int f, int side)
 {
-    return g.halo_buf + (size_t)(2 * IGG_MAX_FIELDS + f * 2 + side) * g.halo_cap;
+    return g.halo_buf + ((size_t)r * 4 * IGG_MAX_FIELDS + 2 * IGG_MAX_FIELDS + f * 2 + side) * g.halo_cap;
 }
 
 int launch_halo(const igg_field *fl, int nf, hipStream_t s, int dims)
 {
     Grid &g = grid();
     for (int d = 0; d < 3; ++d) {
-        if (!g.periods[d]) continue;  // no neighbour in this dimension
         if (!((dims >> d) & 1)) continue;  // done elsewhere (fused into the step)
-        HaloSet hs{};
-        int64_t maxcount = 0;
-        for (int f = 0; f < nf; ++f) {
-            const igg_field &F = fl[f];
-            const int64_t nx = F.size[0], ny = F.size[1], nz = F.size[2];
-            const int nA = (int)F.size[d];
-            const int olA = g.ol[d] + (nA - g.n[d]);
-            HaloDesc base{};
-            base.base = (unsigned char *)F.data;
-            base.esz = elem_bytes(F.dtype);
-            if (d == 0) {
-                base.sd = 1; base.na = (int)ny; base.sa = nx; base.nb = (int)nz; base.sb = nx * ny;
-            } else if (d == 1) {
-                base.sd = nx; base.na = (int)nx; base.sa = 1; base.nb = (int)nz; base.sb = nx * ny;
-            } else {
-                base.sd = nx * ny; base.na = (int)nx; base.sa = 1; base.nb = (int)ny; base.sb = nx;
+        for (int r = 0; r < g.nranks; ++r) {
+            HaloSet hs{};
+            int nd = 0;
+            int64_t maxcount = 0;
+            const int lo_nbr = rank_neighbor(r, d, 0), hi_nbr = rank_neighbor(r, d, 1);
+            for (int f = 0; f < nf; ++f) {
+                const igg_field &F = fl[(size_t)r * nf + f];
+                const int64_t nx = F.size[0], ny = F.size[1], nz = F.size[2];
+                const int nA = (int)F.size[d];
+                const int olA = g.ol[d] + (nA - g.n[d]);
+                HaloDesc base{};
+                base.esz = elem_bytes(F.dtype);
+                if (d == 0) {
+                    base.sd = 1; base.na = (int)ny; base.sa = nx; base.nb = (int)nz; base.sb = nx * ny;
+                } else if (d == 1) {
+                    base.sd = nx; base.na = (int)nx; base.sa = 1; base.nb = (int)nz; base.sb = nx * ny;
+                } else {
+                    base.sd = nx * ny; base.na = (int)nx; base.sa = 1; base.nb = (int)ny; base.sb = nx;
+                }
+                // whole rows as 16-byte vectors where rows, strides and bases allow
+                const int64_t e = base.esz;
+                bool vec = base.sa == 1 && (base.na * e) % 16 == 0 && (base.sb * e) % 16 == 0 &&
+                           (base.sd * e) % 16 == 0 && ((uintptr_t)F.data % 16) == 0;
+                for (int q : {lo_nbr, hi_nbr})
+                    if (q >= 0 && ((uintptr_t)fl[(size_t)q * nf + f].data % 16) != 0) vec = false;
+                if (vec) {
+                    base.na = (int)(base.na * e / 16);
+                    base.sb = base.sb * e / 16;
+                    base.sd = base.sd * e / 16;
+                    base.esz = 16;
+                }
+                base.src_base = (unsigned char *)F.data;
+                if (lo_nbr >= 0) {
+                    // plane ol-1 becomes the lower neighbour's last plane
+                    HaloDesc lo = base;
+                    lo.dst_base = (unsigned char *)fl[(size_t)lo_nbr * nf + f].data;
+                    lo.src = olA - 1;
+                    lo.dst = nA - 1;
+                    lo.send = send_buf(g, r, f, 0);
+                    lo.recv = recv_buf(g, lo_nbr, f, 1);
+                    hs.d[nd++] = lo;
+                }
+                if (hi_nbr >= 0) {
+                    // plane n-ol becomes the upper neighbour's first plane
+                    HaloDesc hi = base;
+                    hi.dst_base = (unsigned char *)fl[(size_t)hi_nbr * nf + f].data;
+                    hi.src = nA - olA;
+                    hi.dst = 0;
+                    hi.send = send_buf(g, r, f, 1);
+                    hi.recv = recv_buf(g, hi_nbr, f, 0);
+                    hs.d[nd++] = hi;
+                }
+                maxcount = std::max(maxcount, (int64_t)base.na * base.nb);
             }
-            // whole rows as 16-byte vectors where rows, strides and base allow
-            const int64_t e = base.esz;
-            if (base.sa == 1 && (base.na * e) % 16 == 0 && (base.sb * e) % 16 == 0 && (base.sd * e) % 16 == 0 &&
-                ((uintptr_t)F.data % 16) == 0) {
-                base.na = (int)(base.na * e / 16);
-                base.sb = base.sb * e / 16;
-                base.sd = base.sd * e / 16;
-                base.esz = 16;
-            }
-            maxcount = std::max(maxcount, (int64_t)base.na * base.nb);
-            HaloDesc lo = base, hi = base;
-            lo.src = olA - 1;  // to the lower neighbour's last plane
-            lo.dst = nA - 1;   // filled from the upper neighbour's plane ol-1
-            lo.send = send_buf(g, f, 0);
-            lo.recv = recv_buf(g, f, 1);
-            hi.src = nA - olA;  // to the upper neighbour's first plane
-            hi.dst = 0;         // filled from the lower neighbour's plane n-ol
-            hi.send = send_buf(g, f, 1);
-            hi.recv = recv_buf(g, f, 0);
-            hs.d[2 * f] = lo;
-            hs.d[2 * f + 1] = hi;
+            if (nd == 0) continue;  // no neighbour in this dimension
+            int64_t b = (maxcount + 255) / 256;
+            dim3 grd((unsigned)std::min<int64_t>(std::max<int64_t>(b, 1), 1024), nd);
+            hipLaunchKernelGGL(k_halo_self, grd, dim3(256), 0, s, hs);
+            IGG_HIP(hipGetLastError());
         }
-        int64_t b = (maxcount + 255) / 256;
-        dim3 grd((unsigned)std::min<int64_t>(std::max<int64_t>(b, 1), 1024), 2 * nf);
-        hipLaunchKernelGGL(k_halo_self, grd, dim3(256), 0, s, hs);
-        IGG_HIP(hipGetLastError());
     }
     return IGG_OK;
 }

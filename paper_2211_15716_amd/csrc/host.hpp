@@ -62,7 +62,8 @@ struct Grid {
     hipEvent_t ev_fork = nullptr;     // caller stream -> helper stream
     hipEvent_t ev_join = nullptr;     // helper stream -> caller stream
 
-    unsigned char *halo_buf = nullptr;  // send and receive planes
+    int nranks = 1;                     // virtual ranks held by this process (product of dims)
+    unsigned char *halo_buf = nullptr;  // send and receive planes of every rank
     size_t halo_cap = 0;                // bytes of one side of one field (one plane)
 
     double *red_part = nullptr;  // per-block partial results
@@ -99,17 +100,36 @@ struct Split {
 int plan_split(const int n[3], const int w[3], Split &s);
 BoxSet make_boxset(const Box *b, int nb);
 
+// ------------------------------------------------------------ ranks
+// Virtual rank r of a dims[0] x dims[1] x dims[2] topology has coordinates
+// (r % dims[0], (r / dims[0]) % dims[1], r / (dims[0] * dims[1])).
+void rank_coords(int r, int c[3]);
+// Neighbour of rank r in dimension d on side s (0 lower, 1 upper), or -1
+// at the edge of a non-periodic dimension.
+int rank_neighbor(int r, int d, int s);
+
 // ------------------------------------------------------------- launchers
-// Halo update of fields (already validated) on `s`.
+// Halo update of fields (already validated) on `s`: fields[r * nf + f] is
+// field f of rank r, for the grid's nranks ranks.
 // dims: bit d set = update dimension d (x = bit 0)
 int launch_halo(const igg_field *f, int nf, hipStream_t s, int dims = 7);
 
-// x exchange fused into a step kernel: when `on`, the point computed at
-// x = lo (ol-1) is also stored at x = nx-1 and the point at x = hi (nx-ol)
-// at x = 0, which is what the periodic x halo update of the result does
-// when this process is its own x neighbour.
+// x exchange fused into a step kernel.  The point computed at x = lo (ol-1)
+// is also stored at x = nx-1 of the lower x neighbour's array (on_lo), the
+// point at x = hi (nx-ol) at x = 0 of the upper neighbour's array (on_hi);
+// d_lo and d_hi are those arrays' offsets from the own array in elements (0
+// when the process is its own neighbour).  That is the x halo update of the
+// result, done by the thread that computes the point.
 struct XHalo {
-    int on, lo, hi;
+    int on_lo, on_hi, lo, hi;
+    int64_t d_lo, d_hi;
+};
+
+// Global origin of a block for the FP16 stochastic-rounding hash: the point
+// (i, j, k) of the block is hashed as (i + ox, j + oy, k + oz) in a global
+// index space gnx points wide, so every decomposition rounds a point alike.
+struct SrOrigin {
+    int ox, oy, oz, gnx;
 };
 
 struct StepArgs {
@@ -121,6 +141,7 @@ struct StepArgs {
     uint32_t key;          // FP16 stochastic-rounding key
     int stochastic;
     XHalo xh;
+    SrOrigin so;
 };
 int launch_step_boxes(int dtype, const StepArgs &a, const Box *b, int nb, hipStream_t s);
 int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s);

@@ -60,7 +60,7 @@ template <typename S>
 __global__ void __launch_bounds__(256)
 k_step_boxes(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__ Ci, BoxSet bs, int nx,
              int ny, compute_t<S> a, compute_t<S> rx, compute_t<S> ry, compute_t<S> rz, uint32_t key,
-             int stochastic, XHalo xh)
+             int stochastic, XHalo xh, SrOrigin so)
 {
     using C = compute_t<S>;
     int i, j, k;
@@ -72,13 +72,11 @@ k_step_boxes(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__ 
     C out = diffuse<C>(c, widen<C>(T[p - 1]), widen<C>(T[p + 1]), widen<C>(T[p - sy]), widen<C>(T[p + sy]),
                        widen<C>(T[p - sz]), widen<C>(T[p + sz]), widen<C>(Ci[p]), a, rx, ry, rz);
     uint32_t r = 0;
-    if (stochastic) r = point_bits(plane_key(key, k), i, j, nx);
+    if (stochastic) r = point_bits(plane_key(key, k + so.oz), i + so.ox, j + so.oy, so.gnx);
     const S v = Store<S>::put(out, r, stochastic);
     T2[p] = v;
-    if (xh.on) {
-        if (i == xh.lo) T2[p - i + nx - 1] = v;
-        if (i == xh.hi) T2[p - i] = v;
-    }
+    if (xh.on_lo && i == xh.lo) T2[p - i + nx - 1 + xh.d_lo] = v;
+    if (xh.on_hi && i == xh.hi) T2[p - i + xh.d_hi] = v;
 }
 
 // --------------------------------------------------------------- z-march
@@ -104,6 +102,7 @@ struct ZTile {
     // x = 2*w2 is column w2 of row j (slabs a full half tile wide).
     int w2, wl0, wl1, wr0, wr1, jr0, jr1, wh;
     XHalo xh;
+    SrOrigin so;
 };
 
 // BX x TY threads; thread (tx, ty) owns RY consecutive rows of VEC points.
@@ -231,7 +230,7 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
             for (int q = 0; q < VEC; ++q) tile[buf][hyrow][1 + tx * VEC + q] = widen<C>(lane_elem<S, VEC>(yh, q));
         }
         __syncthreads();
-        const uint32_t pk = stochastic ? plane_key(key, k) : 0u;
+        const uint32_t pk = stochastic ? plane_key(key, k + z.so.oz) : 0u;
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             if (!crow[r]) continue;
@@ -254,7 +253,7 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
                     ir = left ? ir + nx - z.w2 : ir - z.w2;
                     jreal = left ? jreal - 1 : jreal;
                 }
-                const uint32_t rb = stochastic ? point_bits(pk, ir, jreal, nx) : 0u;
+                const uint32_t rb = stochastic ? point_bits(pk, ir + z.so.ox, jreal + z.so.oy, z.so.gnx) : 0u;
                 set_elem<S, VEC>(out, q, Store<S>::put(v, rb, stochastic));
             }
             S *dst = T2 + (int64_t)k * sxy + col[r];
@@ -282,16 +281,17 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
                 for (int q = 0; q < VEC; ++q)
                     if (i + q >= bb.i0 && i + q < bb.i1) dst[q] = lane_elem<S, VEC>(out, q);
             }
-            // x exchange with this process as its own neighbour (x periodic):
-            // the point at x = ol-1 also fills x = nx-1, the point at
-            // x = nx-ol also fills x = 0
-            if (z.xh.on && rowin && ix <= z.xh.lo && ix + VEC > z.xh.lo) {
+            // x exchange fused into the store: the point at x = ol-1 also
+            // fills x = nx-1 of the lower x neighbour, the point at x = nx-ol
+            // x = 0 of the upper one (this array itself on one periodic rank)
+            if (z.xh.on_lo && rowin && ix <= z.xh.lo && ix + VEC > z.xh.lo) {
                 const int q = z.xh.lo - ix;
-                if (i + q >= c0 && i + q < c1) dst[q + nx - 1 - z.xh.lo] = lane_elem_dyn<S, VEC>(out, q);
+                if (i + q >= c0 && i + q < c1)
+                    dst[q + nx - 1 - z.xh.lo + z.xh.d_lo] = lane_elem_dyn<S, VEC>(out, q);
             }
-            if (z.xh.on && rowin && ix <= z.xh.hi && ix + VEC > z.xh.hi) {
+            if (z.xh.on_hi && rowin && ix <= z.xh.hi && ix + VEC > z.xh.hi) {
                 const int q = z.xh.hi - ix;
-                if (i + q >= c0 && i + q < c1) dst[q - z.xh.hi] = lane_elem_dyn<S, VEC>(out, q);
+                if (i + q >= c0 && i + q < c1) dst[q - z.xh.hi + z.xh.d_hi] = lane_elem_dyn<S, VEC>(out, q);
             }
         }
 #pragma unroll
@@ -323,7 +323,7 @@ static int run_boxes(const StepArgs &a, const Box *b, int nb, hipStream_t s)
     int64_t blocks = (threads + 255) / 256;
     hipLaunchKernelGGL(k_step_boxes<S>, dim3((unsigned)blocks), dim3(256), 0, s, (S *)a.T2,
                        (const S *)a.T, (const S *)a.Ci, bs, a.nx, a.ny, (C)a.a, (C)a.rx, (C)a.ry,
-                       (C)a.rz, a.key, a.stochastic, a.xh);
+                       (C)a.rz, a.key, a.stochastic, a.xh, a.so);
     IGG_HIP(hipGetLastError());
     return IGG_OK;
 }
@@ -366,6 +366,7 @@ static int run_zmarch(const StepArgs &a, const Box *b, int nbox, hipStream_t s, 
     z.nx = a.nx;
     z.ny = a.ny;
     z.xh = a.xh;
+    z.so = a.so;
     int64_t columns = 0;
     int depth_max = 0;
     for (int q = 0; q < nbox; ++q) {

@@ -28,11 +28,13 @@ IGG_ROUND_NEAREST, IGG_ROUND_STOCHASTIC = 0, 1
 
 RED_MAX, RED_MIN, RED_SUM, RED_SUM_RATIO, RED_HALF_SQDIFF, RED_DOT, RED_MAX_ABS_DIFF, RED_MAX_ABS = range(8)
 MAX_FIELDS = 8
+MAX_RANKS = 64
 
 EXPORTS = ["igg_init_global_grid", "igg_global_size", "igg_topology", "igg_update_halo",
            "igg_finalize_global_grid", "diffusion_step", "diffusion_dt", "diffusion_step_adjoint",
            "diffusion_flux_step", "diffusion_flux_step_adjoint", "igg_reduce", "igg_plan_split",
-           "igg_timing_enable", "igg_timing_read", "igg_last_error", "igg_version"]
+           "igg_timing_enable", "igg_timing_read", "igg_last_error", "igg_version",
+           "igg_nranks", "igg_rank_coords", "igg_neighbors", "igg_update_halo_ranks", "diffusion_step_ranks"]
 
 
 class IggError(RuntimeError):
@@ -72,8 +74,13 @@ def load():
     lib.igg_global_size.argtypes = [i64p]
     lib.igg_topology.argtypes = [_PI] * 5
     lib.igg_update_halo.argtypes = [_PF, ctypes.c_int, vp]
+    lib.igg_update_halo_ranks.argtypes = [_PF, ctypes.c_int, vp]
+    lib.igg_nranks.argtypes = [_PI]
+    lib.igg_rank_coords.argtypes = [ctypes.c_int, _PI]
+    lib.igg_neighbors.argtypes = [ctypes.c_int, _PI, _PI]
     lib.igg_finalize_global_grid.argtypes = []
     lib.diffusion_step.argtypes = [_PF] * 3 + [d] * 5 + [_PI, ctypes.POINTER(Rounding), vp]
+    lib.diffusion_step_ranks.argtypes = [_PF] * 3 + [d] * 5 + [_PI, ctypes.POINTER(Rounding), vp]
     lib.diffusion_dt.argtypes = [_PF, d, d, d, d, ctypes.POINTER(d), vp]
     lib.diffusion_step_adjoint.argtypes = [_PF] * 5 + [d] * 5 + [_PI, vp]
     lib.diffusion_flux_step.argtypes = [_PF] * 6 + [d] * 5 + [vp]
@@ -169,6 +176,37 @@ def update_halo(*tensors, stream=None):
     _check(load().igg_update_halo(fs, len(tensors), _stream(stream)))
 
 
+def nranks():
+    """Ranks the grid holds (the product of dims; several = virtual ranks)."""
+    n = ctypes.c_int(0)
+    _check(load().igg_nranks(ctypes.byref(n)))
+    return n.value
+
+
+def rank_coords(rank):
+    c = _INT3()
+    _check(load().igg_rank_coords(int(rank), c))
+    return tuple(c)
+
+
+def neighbors(rank):
+    """(lower, upper) neighbour ranks per dimension, -1 where there is none."""
+    lo, hi = _INT3(), _INT3()
+    _check(load().igg_neighbors(int(rank), lo, hi))
+    return tuple(lo), tuple(hi)
+
+
+def update_halo_ranks(*per_rank, stream=None):
+    """Halo update across the grid's ranks: per_rank[r] is rank r's tuple of
+    fields (the same number of fields for every rank)."""
+    nf = len(per_rank[0])
+    if any(len(fs) != nf for fs in per_rank):
+        raise ValueError("every rank must pass the same number of fields")
+    flat = [t for fs in per_rank for t in fs]
+    arr = (Field * len(flat))(*[field(t) for t in flat])
+    _check(load().igg_update_halo_ranks(arr, nf, _stream(stream)))
+
+
 # ------------------------------------------------------------------ step
 def rounding(mode="stochastic", seed=0, counter=0):
     code = {"nearest": IGG_ROUND_NEAREST, "stochastic": IGG_ROUND_STOCHASTIC}[mode]
@@ -181,6 +219,17 @@ def diffusion_step(T2, T, Ci, lam, dt, dx, dy, dz, split=(16, 2, 2), rnd=None, s
     r = ctypes.byref(rnd) if rnd is not None else None
     _check(load().diffusion_step(ctypes.byref(f2), ctypes.byref(f), ctypes.byref(fc), float(lam), float(dt),
                                  float(dx), float(dy), float(dz), _int3(split), r, _stream(stream)))
+
+
+def diffusion_step_ranks(T2s, Ts, Cis, lam, dt, dx, dy, dz, split=(16, 2, 2), rnd=None, stream=None):
+    """diffusion_step on every rank's block (lists with one tensor per rank)."""
+    P = len(Ts)
+    a2 = (Field * P)(*[field(t) for t in T2s])
+    a = (Field * P)(*[field(t) for t in Ts])
+    ac = (Field * P)(*[field(t) for t in Cis])
+    r = ctypes.byref(rnd) if rnd is not None else None
+    _check(load().diffusion_step_ranks(a2, a, ac, float(lam), float(dt), float(dx), float(dy), float(dz),
+                                       _int3(split), r, _stream(stream)))
 
 
 def diffusion_dt(Ci, lam, dx, dy, dz, stream=None):

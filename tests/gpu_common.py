@@ -18,7 +18,7 @@ def say(*a):
 
 
 @contextlib.contextmanager
-def grid(n, periods=PER, overlaps=(2, 2, 2), zmarch_min=0):
+def grid(n, periods=PER, overlaps=(2, 2, 2), zmarch_min=0, dims=(1, 1, 1)):
     """The global grid for one test.  zmarch_min is the smallest region the
     z-march kernels take (read at init): 0 sends every region through them,
     as the large grids do, so small test grids exercise their tiling; None
@@ -31,7 +31,7 @@ def grid(n, periods=PER, overlaps=(2, 2, 2), zmarch_min=0):
     else:
         os.environ[key] = str(zmarch_min)
     try:
-        igg.init_global_grid(nx, ny, nz, dims=(1, 1, 1), periods=periods, overlaps=overlaps)
+        igg.init_global_grid(nx, ny, nz, dims=dims, periods=periods, overlaps=overlaps)
     finally:
         if old is None:
             os.environ.pop(key, None)

@@ -80,7 +80,7 @@ def test_grid_lifecycle_and_global_size(host_grid):
 
 @pytest.mark.parametrize("args", [
     (2, 8, 8, None, None, None),                      # n < ol + 1
-    (8, 8, 8, (2, 1, 1), None, None),                 # more than one process
+    (8, 8, 8, (8, 4, 4), None, None),                 # more virtual ranks than IGG_MAX_RANKS
     (8, 8, 8, None, (2, 0, 0), None),                 # period not 0/1
     (8, 8, 8, None, None, (1, 2, 2)),                 # overlap < 2
     (8, 8, 8, (-1, 1, 1), None, None),
@@ -178,3 +178,66 @@ def test_split_plan_partitions_inner_points(n, split):
         assert i0 > 1 and j0 > 1 and k0 > 1
     if n == (512, 512, 512):
         assert inner_box == (16, 496, 2, 510, 2, 510)
+
+
+@pytest.mark.parametrize("dims,periods", [((2, 3, 2), (1, 0, 1)), ((1, 1, 4), (0, 0, 1)), ((3, 1, 1), (0, 1, 0)),
+                                          ((2, 2, 2), (1, 1, 1))])
+def test_virtual_ranks_topology(host_grid, dims, periods):
+    """Rank coordinates (x fastest) and neighbours against a brute force over
+    the Cartesian topology; the global size against the oracle's formula."""
+    import oracle
+    n, ol = (10, 8, 7), (2, 3, 2)
+    igg.init_global_grid(*n, dims=dims, periods=periods, overlaps=ol)
+    try:
+        P = dims[0] * dims[1] * dims[2]
+        assert igg.nranks() == P
+        assert igg.global_size() == tuple(oracle.global_size(n, dims, periods, ol))
+        coords = {}
+        for cz in range(dims[2]):
+            for cy in range(dims[1]):
+                for cx in range(dims[0]):
+                    coords[len(coords)] = (cx, cy, cz)
+        inv = {c: r for r, c in coords.items()}
+        for r in range(P):
+            assert igg.rank_coords(r) == coords[r]
+            lo, hi = igg.neighbors(r)
+            for d in range(3):
+                for side, got in ((-1, lo[d]), (1, hi[d])):
+                    c = list(coords[r])
+                    c[d] += side
+                    if 0 <= c[d] < dims[d]:
+                        want = inv[tuple(c)]
+                    elif periods[d]:
+                        c[d] %= dims[d]
+                        want = inv[tuple(c)]
+                    else:
+                        want = -1
+                    assert got == want, (r, d, side)
+        with pytest.raises(igg.IggError):
+            igg.rank_coords(P)
+        if P > 1:
+            # the single-block entry points refuse a grid of several ranks
+            # (a state check made before any argument is looked at)
+            lib = igg.load()
+            assert lib.diffusion_step(None, None, None, 1.0, 1e-3, 0.1, 0.1, 0.1, None, None, None) == \
+                igg.IGG_ERR_STATE
+            assert lib.igg_update_halo(None, 1, None) == igg.IGG_ERR_STATE
+    finally:
+        igg.finalize_global_grid()
+
+
+def test_virtual_ranks_cover_the_global_grid():
+    """The blocks' global index ranges c*(n-ol) + [0, n) tile the global
+    index space 0 .. dims*(n-ol)+ol-1: neighbouring blocks share exactly ol
+    indices and together they cover every index (the decomposition the GPU
+    tests compare against one block of the global size)."""
+    import oracle
+    for n, ol, dims, per in [(10, 2, 3, 1), (9, 3, 2, 0), (12, 4, 4, 1), (5, 2, 1, 1)]:
+        N = dims * (n - ol) + ol
+        cover = np.zeros(N, int)
+        for c in range(dims):
+            cover[c * (n - ol): c * (n - ol) + n] += 1
+        assert cover.min() >= 1 and cover.max() <= 2
+        assert (cover == 2).sum() == (dims - 1) * ol
+        # unique points: N minus the ol periodic images when periodic
+        assert N - ol * per == oracle.global_size((n, n, n), (dims, 1, 1), (per, 0, 0), (ol, ol, ol))[0]

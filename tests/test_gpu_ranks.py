@@ -1,0 +1,121 @@
+"""Virtual ranks: a dims[0] x dims[1] x dims[2] decomposition held as
+separate blocks on one GPU, with the exchange between blocks.  Rank c's
+block is the slice c*(n-ol) .. c*(n-ol)+n-1 of one block of the global size
+N = dims*(n-ol)+ol (per dimension), so the halo update and the time loop on
+the ranks must give that block's values bit for bit, and the global block
+must match the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2211_15716_amd import diffusion, igg, synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+from gpu_common import dev, grid, host, say  # noqa: E402
+
+DT = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16}
+
+
+def _global_n(n, ol, dims):
+    return tuple(d * (m - o) + o for m, o, d in zip(n, ol, dims))
+
+
+def _ranks(dims):
+    return [(cx, cy, cz) for cz in range(dims[2]) for cy in range(dims[1]) for cx in range(dims[0])]
+
+
+def _block(G, c, n, ol, extra=(0, 0, 0)):
+    """Rank c's block of a global array G (z, y, x order); extra adds the
+    staggered point of a face field per dimension."""
+    sl = [slice(cd * (m - o), cd * (m - o) + m + e) for cd, m, o, e in zip(c, n, ol, extra)]
+    return G[sl[2], sl[1], sl[0]]
+
+
+CASES = [
+    ((12, 10, 9), (2, 2, 2), (1, 1, 1), (2, 2, 2)),
+    ((11, 9, 10), (3, 1, 2), (1, 0, 1), (2, 2, 3)),
+    ((10, 12, 8), (1, 3, 1), (0, 1, 0), (3, 2, 2)),
+    ((9, 9, 9), (2, 1, 1), (1, 1, 1), (2, 2, 2)),
+]
+
+
+@pytest.mark.parametrize("n,dims,periods,ol", CASES)
+def test_halo_ranks_equal_global_halo(n, dims, periods, ol):
+    """Each rank's halo planes that have a neighbour are overwritten with
+    garbage; the exchange must restore the global block with its periodic
+    halo (a cell-centred and a staggered field, FP64 and FP32)."""
+    say("halo ranks", n, dims, periods, ol)
+    N = _global_n(n, ol, dims)
+    rng = np.random.default_rng(41)
+    G = rng.uniform(-1, 1, (N[2], N[1], N[0]))
+    Gq = rng.uniform(-1, 1, (N[2], N[1], N[0] + 1))  # x-face field
+    ref = oracle.halo(G.copy(), ol, periods)
+    refq = oracle.halo(Gq.copy(), (ol[0] + 1, ol[1], ol[2]), periods)
+    with grid(n, periods, ol, dims=dims):
+        ranks = _ranks(dims)
+        per_rank = []
+        for r, c in enumerate(ranks):
+            assert igg.rank_coords(r) == c
+            lo, hi = igg.neighbors(r)
+            blocks = []
+            for A, extra, dt in ((G, (0, 0, 0), torch.float64), (Gq, (1, 0, 0), torch.float32)):
+                b = _block(A, c, n, ol, extra).copy()
+                for d in range(3):
+                    ax = 2 - d
+                    if lo[d] >= 0:
+                        np.moveaxis(b, ax, 0)[0] = 1e30
+                    if hi[d] >= 0:
+                        np.moveaxis(b, ax, 0)[-1] = 1e30
+                blocks.append(dev(b, dt))
+            per_rank.append(blocks)
+        igg.update_halo_ranks(*per_rank)
+        for r, c in enumerate(ranks):
+            t, tq = per_rank[r]
+            assert np.array_equal(host(t), _block(ref, c, n, ol)), r
+            want = host(dev(_block(refq, c, n, ol, (1, 0, 0)), torch.float32))
+            assert np.array_equal(host(tq), want), r
+
+
+def _global_problem(N, periods, ol, seed):
+    T0, Ci = synth.noisy_state_uniform_ci(N[0], N[1], N[2], seed=seed, noise=1e-2)
+    oracle.halo(T0, ol, periods)
+    oracle.halo(Ci, ol, periods)
+    return T0, Ci
+
+
+@pytest.mark.parametrize("n,dims,periods,ol", CASES + [((70, 40, 36), (2, 2, 2), (1, 1, 1), (2, 2, 2))])
+@pytest.mark.parametrize("dt_name", ["f64", "f32", "f16"])
+def test_step_ranks_equal_global_block(n, dims, periods, ol, dt_name):
+    """nt steps on the ranks (split and unsplit) give the global block's
+    nt steps bit for bit, halos included; FP64 also matches the oracle."""
+    N = _global_n(n, ol, dims)
+    T0, Ci = _global_problem(N, periods, ol, 43)
+    dx = 1.0 / (N[0] - 1)
+    dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
+    nt = 5
+    seed = 11 if dt_name == "f16" else None
+    wdt = DT[dt_name]
+    with grid(N, periods, ol):
+        say("global block", N, dt_name)
+        glob = host(diffusion.forward(dev(T0, wdt), dev(Ci, wdt), nt, 1.0, dt, dx, dx, dx, split=None,
+                                      sr_seed=seed))
+    if dt_name == "f64":
+        ref = oracle.run(T0, Ci, nt, 1.0, dt, dx, dx, dx, ol=ol, periods=periods)
+        assert np.max(np.abs(glob - ref)) <= 1e-12 * np.max(np.abs(ref))
+    ranks = _ranks(dims)
+    for split in [None, (4, 3, 3), (16, 2, 2)]:
+        if split is not None and any(w < o for w, o in zip(split, ol)):
+            continue
+        with grid(n, periods, ol, dims=dims):
+            say("step ranks", n, dims, periods, ol, dt_name, split)
+            Ts = [dev(_block(T0, c, n, ol), wdt) for c in ranks]
+            Cs = [dev(_block(Ci, c, n, ol), wdt) for c in ranks]
+            Ws = [t.clone() for t in Ts]
+            a, b = Ts, Ws
+            for it in range(nt):
+                rnd = igg.rounding("stochastic", seed, it) if seed is not None else None
+                igg.diffusion_step_ranks(b, a, Cs, 1.0, dt, dx, dx, dx, split=split, rnd=rnd)
+                a, b = b, a
+            for r, c in enumerate(ranks):
+                assert np.array_equal(host(a[r]), _block(glob, c, n, ol)), (split, r, c)
