@@ -25,7 +25,9 @@ Also reported on the same line:
                 one step on one core;
   variants      FP32 and FP16-storage steps at 512^3 (noisy-bump recipe,
                 uniform Ci) with their error against the FP64 result, the
-                unsplit FP64 step, and the checkpointed adjoint.
+                unsplit FP64 step, the checkpointed adjoint at 256^3, the
+                32^3 launch-bound step (eager and graph), and the 768^3
+                staggered flux form in FP32 with its checkpointed adjoint.
 """
 import argparse
 import hashlib
@@ -380,6 +382,8 @@ def main():
     result["variants"]["adjoint_256"] = adjoint_variant(igg, torch, synth)
     # ---------------------------------------------------------------- small grid: eager vs graph
     result["variants"]["c1_32_launch_bound"] = small_grid_variant(igg, torch, synth)
+    # ---------------------------------------------------------------- staggered flux form
+    result["variants"]["flux_768_fp32"] = flux_variant(igg, torch, synth, K)
 
     print(json.dumps(result), flush=True)
 
@@ -431,6 +435,84 @@ def adjoint_variant(igg, torch, synth):
     del T, Ctrue, O, C, gT, gC, sw, sw2
     torch.cuda.empty_cache()
     igg.finalize_global_grid()
+    return out
+
+
+def flux_variant(igg, torch, synth, K):
+    """768^3 staggered flux form in FP32 (cells 768^3, faces 769 x 768^2 per
+    component): K timed steps (the fused face-and-cell pass, halo update of
+    T2, qx, qy, qz); 100 steps in FP32 and FP64 for the error; the
+    checkpointed adjoint (sqrt(nt) snapshots) of 0.5*||T_nt - T0||^2 over
+    nt = 100 steps in FP32 and FP64, and the gradients' difference.
+    Algorithmic bytes of the method as two passes: 10*s per cell per step
+    (flux: T read, three faces written; update: T, Ci and three faces read,
+    T2 written); the fused pass needs only 6*s (the faces are not read
+    back), reported beside it."""
+    from paper_2211_15716_amd import diffusion
+    w = synth.workload("c5_768_flux", seed=0)
+    n = w["nx"]
+    d = (w["dx"], w["dy"], w["dz"])
+    lam = w["lam"]
+    nt = w["nt"]
+    pts = float(n) ** 3
+    igg.init_global_grid(n, n, n, dims=(1, 1, 1), periods=(1, 1, 1), overlaps=(2, 2, 2))
+    T64, C64 = diffusion.prepare_fields(w["T0"], w["Ci"])
+    del w
+    dt = igg.diffusion_dt(C64, lam, *d)
+    out = {"grid": [n, n, n], "nt": nt, "bytes_per_cell": 40}
+    finals = {}
+    for name, tdt in (("f32", torch.float32), ("f64", torch.float64)):
+        T = T64.to(tdt).contiguous()
+        C = C64.to(tdt).contiguous()
+        prob = diffusion.FluxProblem(lam, dt, *d)
+        a, b = T.clone(), T.clone()
+        for _ in range(nt):
+            prob.step(b, a, C)
+            a, b = b, a
+        finals[name] = a.to(torch.float64)
+        if name == "f32":
+            for _ in range(3):
+                prob.step(b, a, C)
+                a, b = b, a
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(K):
+                prob.step(b, a, C)
+                a, b = b, a
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / K
+            # T_eff by the two-pass count (40 B per cell), and the rate of the
+            # least traffic the fused pass needs (T, Ci read; T2, qx, qy, qz
+            # written: 24 B per cell), which is what HBM actually has to carry
+            out.update({"ms_per_step": round(ms, 4), "T_eff_GBs": round(40.0 * pts / (ms * 1e-3) / 1e9, 1),
+                        "hbm_frac": round(40.0 * pts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                        "fused_min_bytes_per_cell": 24,
+                        "fused_min_traffic_GBs": round(24.0 * pts / (ms * 1e-3) / 1e9, 1),
+                        "fused_min_traffic_frac": round(24.0 * pts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+        del a, b
+        # checkpointed adjoint, sqrt(nt) snapshots
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L, gT, gC, sw = diffusion.loss_and_grad(T, C, T, prob, nt, ("sqrt",))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        finals[name + "_grad"] = (gT.to(torch.float64), gC.to(torch.float64))
+        out[f"adjoint_{name}"] = {"ms_total": round(el * 1e3, 1), "forward_steps": sw.advances,
+                                  "adjoint_steps": sw.adjoints, "peak_snapshots": sw.peak, "loss": L}
+        del T, C, gT, gC, sw, prob
+        torch.cuda.empty_cache()
+    ref = finals["f64"][1:-1, 1:-1, 1:-1]
+    out["err_f32_vs_f64"] = (finals["f32"][1:-1, 1:-1, 1:-1] - ref).abs().max().item() / ref.abs().max().item()
+    for q, nm in ((0, "dT0"), (1, "dCi")):
+        g64 = finals["f64_grad"][q][1:-1, 1:-1, 1:-1]
+        g32 = finals["f32_grad"][q][1:-1, 1:-1, 1:-1]
+        out[f"grad_{nm}_err_f32_vs_f64"] = (g32 - g64).abs().max().item() / g64.abs().max().item()
+    del finals, ref, T64, C64
+    torch.cuda.empty_cache()
+    igg.finalize_global_grid()
+    log(f"flux form 768^3 FP32: {out.get('ms_per_step')} ms/step, err vs FP64 {out['err_f32_vs_f64']:.2e}")
     return out
 
 

@@ -237,11 +237,20 @@ int diffusion_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1,
  * qz (nx,ny,nz+1) with face f between cells f-1 and f,
  *   qx[f] = -lam*(T[f]-T[f-1])/dx       faces 1..nx-1 of the inner rows
  *   T2    = T - dt*Ci*((qx[i+1]-qx[i])/dx + (qy[j+1]-qy[j])/dy + (qz[k+1]-qz[k])/dz)
- * then one halo update of {T2, qx, qy, qz}.  FP64 or FP32.  split: NULL (no
- * overlap) only in this version.  Errors: as diffusion_step. */
+ * then one halo update of {T2, qx, qy, qz}.  FP64 or FP32.  One pass per
+ * cell computes its lower faces (and the upper face of the last cell of a
+ * row, column or plane), the update from its six faces, and, for periodic
+ * x, the x exchange of all four fields; the values equal a face pass
+ * followed by a cell pass.
+ *   split  boundary widths as in diffusion_step, each >= overlap + 1 (the
+ *          face fields overlap by one more plane in their own dimension);
+ *          the y and z slabs are computed first, the halo update of the four
+ *          fields follows them on the helper stream beside the inner
+ *          region.  NULL = no overlap.
+ * Errors: as diffusion_step (IGG_ERR_ARG for a split width below ol+1). */
 int diffusion_flux_step(const igg_field *T2, const igg_field *T, const igg_field *Ci,
                         const igg_field *qx, const igg_field *qy, const igg_field *qz, double lam,
-                        double dt, double dx, double dy, double dz, void *stream);
+                        double dt, double dx, double dy, double dz, const int split[3], void *stream);
 
 /* Adjoint of diffusion_flux_step: with mu = Ci.*lam_np1 and the adjoint face
  * fluxes p = -lam*grad(mu) (written into px, py, pz, face-field sized work

@@ -266,7 +266,7 @@ static int check_spacings(double lam, double dt, double dx, double dy, double dz
 // boundary(r, slabs, stream) and inner(r, box, stream) launch rank r's
 // kernels; out holds the updated field of every rank.
 template <typename BoundaryLaunch, typename InnerLaunch>
-static int run_split(const int *split, const igg_field *out, int halo_dims, BoundaryLaunch boundary,
+static int run_split(const int *split, const igg_field *out, int nout, int halo_dims, BoundaryLaunch boundary,
                      InnerLaunch inner_launch, hipStream_t s)
 {
     Grid &g = grid();
@@ -299,13 +299,13 @@ static int run_split(const int *split, const igg_field *out, int halo_dims, Boun
         if ((rc = timing_mark(bs, 1))) return rc;
     }
     if (serial) {
-        if ((rc = launch_halo(out, 1, s, halo_dims))) return rc;
+        if ((rc = launch_halo(out, nout, s, halo_dims))) return rc;
     } else {
         if (!on_side) {
             IGG_HIP(hipEventRecord(g.ev_fork, s));
             IGG_HIP(hipStreamWaitEvent(g.side, g.ev_fork, 0));
         }
-        if ((rc = launch_halo(out, 1, g.side, halo_dims))) return rc;
+        if ((rc = launch_halo(out, nout, g.side, halo_dims))) return rc;
         IGG_HIP(hipEventRecord(g.ev_join, g.side));
     }
     for (int r = 0; r < g.nranks && box_points(inner) > 0; ++r) {
@@ -401,7 +401,7 @@ static int step_ranks(const igg_field *T2, const igg_field *T, const igg_field *
         return launch_halo(T2, 1, s, halo_dims);
     }
     return run_split(
-        split, T2, halo_dims,
+        split, T2, 1, halo_dims,
         [&](int r, const Split &b, hipStream_t st) { return launch_step_boundary(dtype, args[r], b, st); },
         [&](int r, const Box &b, hipStream_t st) { return launch_step_inner(dtype, args[r], b, st); }, s);
 }
@@ -675,7 +675,7 @@ int diffusion_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1,
         return launch_halo(lam_n, 1, s, halo_dims);
     }
     return run_split(
-        split, lam_n, halo_dims,
+        split, lam_n, 1, halo_dims,
         [&](int, const Split &b, hipStream_t st) { return launch_adjoint_boxes(dt_, a, b.boundary, b.nb, st); },
         [&](int, const Box &b, hipStream_t st) { return launch_adjoint_inner(dt_, a, b, st); }, s);
 }
@@ -694,7 +694,7 @@ static int check_face(const igg_field *q, const char *name, int dim)
 
 int diffusion_flux_step(const igg_field *T2, const igg_field *T, const igg_field *Ci,
                         const igg_field *qx, const igg_field *qy, const igg_field *qz, double lam,
-                        double dt, double dx, double dy, double dz, void *stream)
+                        double dt, double dx, double dy, double dz, const int split[3], void *stream)
 {
     Grid &g = grid();
     if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
@@ -718,17 +718,31 @@ int diffusion_flux_step(const igg_field *T2, const igg_field *T, const igg_field
             if (overlaps_mem(*outs[o], *outs[p])) return fail(IGG_ERR_ALIAS, "outputs share memory");
     }
     if ((rc = check_spacings(lam, dt, dx, dy, dz))) return rc;
+    // the face fields overlap their neighbours by ol+1 planes in their own
+    // dimension, so each split width must cover that many planes
+    const int olf[3] = {g.ol[0] + 1, g.ol[1] + 1, g.ol[2] + 1};
+    if ((rc = check_split(split, olf))) return rc;
     if ((rc = ensure_device())) return rc;
     hipStream_t s = (hipStream_t)stream;
+    // the x exchange of all four fields is stored by the step kernels when x
+    // is periodic; the halo update then moves y and z
+    const int xon = (g.fuse_x && g.periods[0]) ? 1 : 0;
+    const int halo_dims = g.fuse_x ? 6 : 7;
     FluxArgs a{qx->data, qy->data, qz->data, T->data, T2->data, Ci->data, g.n[0], g.n[1], g.n[2],
-               lam, dt, 1.0 / dx, 1.0 / dy, 1.0 / dz};
-    if ((rc = launch_flux(ty, a, s))) return rc;
-    if ((rc = timing_mark(s, 0))) return rc;
-    if ((rc = launch_flux_update(ty, a, s))) return rc;
-    if ((rc = timing_mark(s, 0))) return rc;
-    if (g.timing) { g.t_launches++; g.t_points += (int64_t)(g.n[0] - 2) * (g.n[1] - 2) * (g.n[2] - 2); }
+               lam, dt, 1.0 / dx, 1.0 / dy, 1.0 / dz, ty, xon, g.ol[0]};
     igg_field hf[4] = {*T2, *qx, *qy, *qz};
-    return launch_halo(hf, 4, s);
+    if (!split) {
+        Box all{1, g.n[0] - 1, 1, g.n[1] - 1, 1, g.n[2] - 1};
+        if ((rc = timing_mark(s, 0))) return rc;
+        if ((rc = launch_flux_inner(ty, a, all, s))) return rc;
+        if ((rc = timing_mark(s, 0))) return rc;
+        if (g.timing) { g.t_launches++; g.t_points += box_points(all); }
+        return launch_halo(hf, 4, s, halo_dims);
+    }
+    return run_split(
+        split, hf, 4, halo_dims,
+        [&](int, const Split &b, hipStream_t st) { return launch_flux_boxes(ty, a, b.boundary, b.nb, st); },
+        [&](int, const Box &b, hipStream_t st) { return launch_flux_inner(ty, a, b, st); }, s);
 }
 
 int diffusion_flux_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1,

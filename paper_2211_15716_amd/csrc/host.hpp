@@ -167,9 +167,13 @@ struct FluxArgs {
     const void *Ci;
     int nx, ny, nz;
     double lam, dt, rdx, rdy, rdz;
+    int dtype;
+    int xon, ol;  // x exchange of T2, qx, qy, qz fused into the stores; the x overlap
 };
-int launch_flux(int dtype, const FluxArgs &a, hipStream_t s);
-int launch_flux_update(int dtype, const FluxArgs &a, hipStream_t s);
+// The fused flux-form step (faces, update, x exchange) over boxes of cells:
+// one thread per cell, or z-march tiles for a large region.
+int launch_flux_boxes(int dtype, const FluxArgs &a, const Box *b, int nb, hipStream_t s);
+int launch_flux_inner(int dtype, const FluxArgs &a, const Box &b, hipStream_t s);
 
 struct FluxAdjArgs {
     void *lam_n;

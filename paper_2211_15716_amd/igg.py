@@ -83,7 +83,7 @@ def load():
     lib.diffusion_step_ranks.argtypes = [_PF] * 3 + [d] * 5 + [_PI, ctypes.POINTER(Rounding), vp]
     lib.diffusion_dt.argtypes = [_PF, d, d, d, d, ctypes.POINTER(d), vp]
     lib.diffusion_step_adjoint.argtypes = [_PF] * 5 + [d] * 5 + [_PI, vp]
-    lib.diffusion_flux_step.argtypes = [_PF] * 6 + [d] * 5 + [vp]
+    lib.diffusion_flux_step.argtypes = [_PF] * 6 + [d] * 5 + [_PI, vp]
     lib.diffusion_flux_step_adjoint.argtypes = [_PF] * 10 + [d] * 5 + [vp]
     lib.igg_reduce.argtypes = [ctypes.c_int, _PF, _PF, ctypes.POINTER(d), vp]
     lib.igg_plan_split.argtypes = [_PI, _PI, (ctypes.c_int * 6) * 7, _PI]
@@ -246,10 +246,12 @@ def diffusion_step_adjoint(lam_n, lam_np1, T_n, Ci, gCi, lam, dt, dx, dy, dz, sp
                                          float(dy), float(dz), _int3(split), _stream(stream)))
 
 
-def diffusion_flux_step(T2, T, Ci, qx, qy, qz, lam, dt, dx, dy, dz, stream=None):
+def diffusion_flux_step(T2, T, Ci, qx, qy, qz, lam, dt, dx, dy, dz, split=None, stream=None):
+    """Staggered flux form of the step plus the halo update of T2, qx, qy, qz
+    (boundary-first when split is given; widths >= overlap + 1)."""
     fs = [field(t) for t in (T2, T, Ci, qx, qy, qz)]
     _check(load().diffusion_flux_step(*[ctypes.byref(f) for f in fs], float(lam), float(dt), float(dx),
-                                      float(dy), float(dz), _stream(stream)))
+                                      float(dy), float(dz), _int3(split), _stream(stream)))
 
 
 def diffusion_flux_step_adjoint(lam_n, lam_np1, Ci, qx, qy, qz, px, py, pz, gCi, lam, dt, dx, dy, dz,

@@ -136,7 +136,13 @@ def test_step_validation_before_any_hip_call(host_grid):
     # flux form: face sizes checked
     q = [_field(0x40000000 + 0x1000000 * d, igg.IGG_F64, n) for d in range(3)]
     assert lib.diffusion_flux_step(r(T2), r(T), r(C), *[r(x) for x in q], 1.0, 1e-3, .1, .1, .1,
-                                   None) == igg.IGG_ERR_SIZE
+                                   None, None) == igg.IGG_ERR_SIZE
+    # flux form: split widths must cover the face fields' overlap ol + 1
+    qf = [_field(0x40000000 + 0x1000000 * d, igg.IGG_F64, tuple(m + (e == d) for e, m in enumerate(n)))
+          for d in range(3)]
+    I3s = ctypes.c_int * 3
+    assert lib.diffusion_flux_step(r(T2), r(T), r(C), *[r(x) for x in qf], 1.0, 1e-3, .1, .1, .1,
+                                   I3s(16, 2, 2), None) == igg.IGG_ERR_ARG
     # reductions
     out = ctypes.c_double()
     assert lib.igg_reduce(99, r(T), None, r(out), None) == igg.IGG_ERR_ARG

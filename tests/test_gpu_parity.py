@@ -371,3 +371,47 @@ def test_flux_form_matches_oracle():
     assert rel_max_err(got, ref) <= 1e-12
     for a, b in zip(qs, qref):
         assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("periods", [(1, 1, 1), (0, 1, 1), (1, 0, 1)])
+def test_flux_form_splits_schedules_and_x_forms(periods, monkeypatch):
+    """The fused flux-form step under every split (widths >= overlap + 1),
+    schedule and x-exchange form: T and the three face fields equal the
+    unsplit run bit for bit, halos included, and the oracle within 1e-12."""
+    n = (70, 30, 26)
+    nx, ny, nz = n
+    T0, Ci = synth.noisy_state_uniform_ci(nx, ny, nz, seed=8, noise=1e-2)
+    oracle.halo(T0, (2, 2, 2), periods)
+    oracle.halo(Ci, (2, 2, 2), periods)
+    d = (1 / 69, 1 / 29, 1 / 25)
+    dt = oracle.time_step(*d, 1.0, oracle.max_all(Ci))
+    nt = 5
+    ref, qref = oracle.flux_run(T0, Ci, nt, 1.0, dt, *d, periods=periods, return_q=True)
+    outs = []
+    for sched, xform in (("1", "fused"), ("0", "halo"), ("2", "fused"), ("1", "halo")):
+        monkeypatch.setenv("IGG_SCHEDULE", sched)
+        monkeypatch.setenv("IGG_X_EXCHANGE", xform)
+        with grid(n, periods):
+            for split in [None, (16, 3, 3), (3, 3, 3), (5, 4, 3)]:
+                say("flux", periods, sched, xform, split)
+                T, C = dev(T0), dev(Ci)
+                T2 = T.clone()
+                q = [torch.zeros(s, dtype=torch.float64, device="cuda") for s in oracle.face_shapes(T0)]
+                for _ in range(nt):
+                    igg.diffusion_flux_step(T2, T, C, *q, 1.0, dt, *d, split=split)
+                    T, T2 = T2, T
+                outs.append([host(T)] + [host(x) for x in q])
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
+    assert np.max(np.abs(outs[0][0] - ref)) <= 1e-12 * np.max(np.abs(ref))
+    for a, b in zip(outs[0][1:], qref):
+        assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
+
+
+def test_flux_split_below_face_overlap_is_rejected():
+    with grid((20, 18, 16)):
+        T = torch.ones((16, 18, 20), dtype=torch.float64, device="cuda")
+        q = [torch.zeros(s, dtype=torch.float64, device="cuda") for s in oracle.face_shapes(host(T))]
+        with pytest.raises(igg.IggError):
+            igg.diffusion_flux_step(T.clone(), T, T, *q, 1.0, 1e-4, 0.1, 0.1, 0.1, split=(16, 2, 2))
