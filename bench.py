@@ -416,23 +416,35 @@ def adjoint_variant(igg, torch, synth):
     igg.timing_enable(False)
     k_ms, k_launches, k_pts, b_ms = igg.timing_read()
     nbytes = (24.0 * sw.advances + 48.0 * sw.adjoints) * pts
-    # the forward sweep alone, to split the time
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    # the same gradient with events between the sweeps: the reverse sweep's
+    # own time (adjoint steps plus the recomputation inside each segment)
     sw2 = diffusion.Sweep(prob, C, T, diffusion.checkpoint_ops(*sched[:1], nt, *sched[1:]))
-    sw2.forward(nt)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     torch.cuda.synchronize()
-    fwd = time.perf_counter() - t1
-    rev_ms = (el - fwd) * 1e3 / nt
-    rev_bytes = (72.0 * pts)
+    ev[0].record()
+    Tnt = sw2.forward(nt)
+    ev[1].record()
+    fwd_adv = sw2.advances
+    lam_nt = diffusion._inner_only(Tnt - O)
+    igg.update_halo(lam_nt)
+    sw2.reverse(lam_nt)
+    ev[2].record()
+    torch.cuda.synchronize()
+    rev_ms = ev[1].elapsed_time(ev[2])
+    recompute = sw2.advances - fwd_adv
+    rev_bytes = (48.0 * sw2.adjoints + 24.0 * recompute) * pts
     out = {"grid": [n, n, n], "nt": nt, "schedule": "periodic every 16", "ms_total": round(el * 1e3, 3),
            "forward_steps": sw.advances, "adjoint_steps": sw.adjoints, "peak_snapshots": sw.peak,
            "T_eff_GBs": round(nbytes / el / 1e9, 1), "hbm_frac": round(nbytes / el / 1e9 / HBM_PEAK_GBS, 4),
-           "ms_per_reverse_step": round(rev_ms, 4),
-           "reverse_step_T_eff_GBs": round(rev_bytes / (rev_ms * 1e-3) / 1e9, 1),
+           "forward_sweep_ms": round(ev[0].elapsed_time(ev[1]), 3),
+           "ms_per_reverse_step": round(rev_ms / nt, 4),
+           "reverse_recompute_steps": recompute,
+           "reverse_T_eff_GBs": round(rev_bytes / (rev_ms * 1e-3) / 1e9, 1),
+           "reverse_hbm_frac": round(rev_bytes / (rev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
            "loss": L}
+    rev_ms = rev_ms / nt
     log(f"adjoint 256^3: {el*1e3:.1f} ms, T_eff {out['T_eff_GBs']} GB/s, reverse step {rev_ms:.4f} ms")
-    del T, Ctrue, O, C, gT, gC, sw, sw2
+    del T, Ctrue, O, C, gT, gC, sw, sw2, Tnt, lam_nt
     torch.cuda.empty_cache()
     igg.finalize_global_grid()
     return out
