@@ -10,9 +10,16 @@ torch = pytest.importorskip("torch")
 from gpu_common import dev, grid, host, say  # noqa: E402
 
 
-@pytest.mark.parametrize("n,split", [((32, 32, 32), (16, 2, 2)), ((66, 40, 36), (16, 2, 2)), ((48, 40, 36), None)])
-def test_graph_replay_matches_eager(n, split):
-    say("graph", n, split)
+@pytest.mark.parametrize("n,split,sched", [((32, 32, 32), (16, 2, 2), None), ((66, 40, 36), (16, 2, 2), None),
+                                           ((48, 40, 36), None, None), ((66, 40, 36), (16, 2, 2), "1"),
+                                           ((66, 40, 36), (16, 2, 2), "0"), ((160, 140, 120), (16, 2, 2), None)])
+def test_graph_replay_matches_eager(n, split, sched, monkeypatch):
+    """Every schedule is capturable: the helper-stream forms (1, and 0)
+    capture their fork and join events as graph edges; 160x140x120 takes
+    schedule 1 by default."""
+    if sched is not None:
+        monkeypatch.setenv("IGG_SCHEDULE", sched)
+    say("graph", n, split, sched)
     w = synth.noisy_state_uniform_ci(*n, seed=71, noise=1e-2)
     T0, Ci = w
     oracle.halo(T0)
