@@ -252,16 +252,17 @@ int diffusion_flux_step(const igg_field *T2, const igg_field *T, const igg_field
                         const igg_field *qx, const igg_field *qy, const igg_field *qz, double lam,
                         double dt, double dx, double dy, double dz, const int split[3], void *stream);
 
-/* Adjoint of diffusion_flux_step: with mu = Ci.*lam_np1 and the adjoint face
- * fluxes p = -lam*grad(mu) (written into px, py, pz, face-field sized work
- * arrays), lam_n = lam_np1 - dt*div(p) on inner cells, then halo(lam_n), and
- * gCi += -dt*lam_np1.*div(q_n) with q_n = (qx,qy,qz) the forward fluxes of
- * step n.  Errors: as diffusion_step_adjoint. */
-int diffusion_flux_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1,
-                                const igg_field *Ci, const igg_field *qx, const igg_field *qy,
-                                const igg_field *qz, const igg_field *px, const igg_field *py,
-                                const igg_field *pz, const igg_field *gCi, double lam, double dt,
-                                double dx, double dy, double dz, void *stream);
+/* Adjoint of diffusion_flux_step.  With mu = Ci.*lam_np1 and the face
+ * fluxes p = -lam*grad(mu) and q_n = -lam*grad(T_n) (the forward fluxes of
+ * step n) formed per cell from its neighbours, as the forward pass forms q:
+ *   lam_n = lam_np1 - dt*div(p)              (inner cells), then halo(lam_n)
+ *   gCi  += -dt*lam_np1.*div(q_n)            (inner cells; halo untouched)
+ * T_n is the state the forward step read (valid halo); Ci needs a valid
+ * halo.  FP64 or FP32.  `split` as in diffusion_step (widths >= overlap).
+ * Errors: as diffusion_step_adjoint. */
+int diffusion_flux_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1, const igg_field *T_n,
+                                const igg_field *Ci, const igg_field *gCi, double lam, double dt, double dx,
+                                double dy, double dz, const int split[3], void *stream);
 
 /* --------------------------------------------------------- reductions */
 

@@ -1,4 +1,5 @@
-// adjoint.hip -- transposed diffusion step.
+// adjoint.hip -- transposed diffusion step, for the Laplacian form and the
+// staggered flux form.
 //
 // The forward step is T_{n+1} = T_n + a*Ci.*(L T_n) on the inner points
 // (a = dt*lam, L = sum_d d2_d/dd^2, symmetric on the periodic grid).  Given
@@ -23,11 +24,38 @@ __device__ __forceinline__ void adjoint_point(C l, C lapmu, C lapT, C a, C &lam_
     g = fma_(a * l, lapT, g);
 }
 
-template <typename C>
+// One cell of the adjoint from mu = Ci.*lp and T_n at the cell and its six
+// neighbours.  FORM 0, the Laplacian step (a = dt*lam, r = 1/dd^2):
+//   lam_n = lp + a*L(mu),  gCi += a*lp*L(T_n).
+// FORM 1, the staggered flux form (a = dt, r = 1/dd, lamf = lam), with the
+// face fluxes p = -lam*grad(mu) and q = -lam*grad(T_n) formed on the fly:
+//   lam_n = lp - dt*div(p),  gCi += -dt*lp*div(q).
+template <typename C, int FORM>
+__device__ __forceinline__ void adj_cell(C l, C m0, C mxm, C mxp, C mym, C myp, C mzm, C mzp, C t0, C txm,
+                                         C txp, C tym, C typ, C tzm, C tzp, C a, C rx, C ry, C rz, C lamf,
+                                         C &ln, C &g)
+{
+    if constexpr (FORM == 0) {
+        const C lapmu = laplace<C>(m0, mxm, mxp, mym, myp, mzm, mzp, rx, ry, rz);
+        const C lapT = laplace<C>(t0, txm, txp, tym, typ, tzm, tzp, rx, ry, rz);
+        adjoint_point<C>(l, lapmu, lapT, a, ln, g);
+    } else {
+        const C divp = flux_div<C>(face_flux<C>(m0, mxm, lamf, rx), face_flux<C>(mxp, m0, lamf, rx),
+                                   face_flux<C>(m0, mym, lamf, ry), face_flux<C>(myp, m0, lamf, ry),
+                                   face_flux<C>(m0, mzm, lamf, rz), face_flux<C>(mzp, m0, lamf, rz), rx, ry, rz);
+        const C divq = flux_div<C>(face_flux<C>(t0, txm, lamf, rx), face_flux<C>(txp, t0, lamf, rx),
+                                   face_flux<C>(t0, tym, lamf, ry), face_flux<C>(typ, t0, lamf, ry),
+                                   face_flux<C>(t0, tzm, lamf, rz), face_flux<C>(tzp, t0, lamf, rz), rx, ry, rz);
+        ln = fma_(-a, divp, l);
+        g = fma_(-a * l, divq, g);
+    }
+}
+
+template <typename C, int FORM>
 __global__ void __launch_bounds__(256)
 k_adj_boxes(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restrict__ Tn,
             const C *__restrict__ Ci, C *__restrict__ gCi, BoxSet bs, int nx, int ny, C a, C rx, C ry,
-            C rz, XHalo xh)
+            C rz, C lamf, XHalo xh)
 {
     int i, j, k;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -35,12 +63,10 @@ k_adj_boxes(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restrict
     const int64_t sy = nx, sz = (int64_t)nx * ny;
     const int64_t p = i + sy * j + sz * k;
     auto mu = [&](int64_t q) { return Ci[q] * lp[q]; };
-    C lapmu = laplace<C>(mu(p), mu(p - 1), mu(p + 1), mu(p - sy), mu(p + sy), mu(p - sz), mu(p + sz), rx,
-                         ry, rz);
-    C lapT = laplace<C>(Tn[p], Tn[p - 1], Tn[p + 1], Tn[p - sy], Tn[p + sy], Tn[p - sz], Tn[p + sz], rx, ry,
-                        rz);
     C ln, g = gCi[p];
-    adjoint_point<C>(lp[p], lapmu, lapT, a, ln, g);
+    adj_cell<C, FORM>(lp[p], mu(p), mu(p - 1), mu(p + 1), mu(p - sy), mu(p + sy), mu(p - sz), mu(p + sz), Tn[p],
+                      Tn[p - 1], Tn[p + 1], Tn[p - sy], Tn[p + sy], Tn[p - sz], Tn[p + sz], a, rx, ry, rz, lamf,
+                      ln, g);
     lam_n[p] = ln;
     gCi[p] = g;
     // x exchange of lam_n fused into the store
@@ -96,10 +122,10 @@ __device__ __forceinline__ void set_el(typename AVec<C, VEC>::type &v, int q, C 
 // double-buffered LDS tiles; lp, mu and T_n of planes k-1..k+1 (k+2 in
 // flight) sit in registers.  gCi is read and written once per point and
 // lam_n written once: non-temporal.
-template <typename C, int VEC, int BX, int TY, int RY>
+template <typename C, int VEC, int BX, int TY, int RY, int FORM>
 __global__ void __launch_bounds__(BX *TY)
 k_adj_zmarch(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restrict__ Tn,
-             const C *__restrict__ Ci, C *__restrict__ gCi, AdjTile z, C a, C rx, C ry, C rz)
+             const C *__restrict__ Ci, C *__restrict__ gCi, AdjTile z, C a, C rx, C ry, C rz, C lamf)
 {
     using V = typename AVec<C, VEC>::type;
     constexpr int TW = BX * VEC, TH = TY * RY, LH = TH + 2, LW = TW + 2;
@@ -236,10 +262,10 @@ k_adj_zmarch(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restric
                 const C txp = (q == VEC - 1) ? sT[buf][lr][lc_ + 1] : el<C, VEC>(tc[r], q + 1);
                 const C tym = (r == 0) ? sT[buf][lr - 1][lc_] : el<C, VEC>(tc[r - 1], q);
                 const C typ = (r == RY - 1) ? sT[buf][lr + 1][lc_] : el<C, VEC>(tc[r + 1], q);
-                const C lapmu = laplace<C>(m0, mxm, mxp, mym, myp, el<C, VEC>(mm[r], q), el<C, VEC>(mp[r], q), rx, ry, rz);
-                const C lapT = laplace<C>(t0, txm, txp, tym, typ, el<C, VEC>(tm[r], q), el<C, VEC>(tp[r], q), rx, ry, rz);
                 C ln, gg = el<C, VEC>(gc[r], q);
-                adjoint_point<C>(el<C, VEC>(lc[r], q), lapmu, lapT, a, ln, gg);
+                adj_cell<C, FORM>(el<C, VEC>(lc[r], q), m0, mxm, mxp, mym, myp, el<C, VEC>(mm[r], q),
+                                  el<C, VEC>(mp[r], q), t0, txm, txp, tym, typ, el<C, VEC>(tm[r], q),
+                                  el<C, VEC>(tp[r], q), a, rx, ry, rz, lamf, ln, gg);
                 set_el<C, VEC>(lo, q, ln);
                 set_el<C, VEC>(go, q, gg);
             }
@@ -286,25 +312,26 @@ static int env_int(const char *name, int dflt)
     return (s && *s) ? atoi(s) : dflt;
 }
 
-template <typename C>
+template <typename C, int FORM>
 static int run_boxes(const AdjArgs &a, const Box *b, int nb, hipStream_t s)
 {
     BoxSet bs = make_boxset(b, nb);
     int64_t threads = bs.first[nb];
     if (threads == 0) return IGG_OK;
-    hipLaunchKernelGGL(k_adj_boxes<C>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_adj_boxes<C, FORM>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
                        (C *)a.lam_n, (const C *)a.lp, (const C *)a.Tn, (const C *)a.Ci, (C *)a.gCi, bs,
-                       a.nx, a.ny, (C)a.a, (C)a.rx, (C)a.ry, (C)a.rz, a.xh);
+                       a.nx, a.ny, (C)a.a, (C)a.rx, (C)a.ry, (C)a.rz, (C)a.lamf, a.xh);
     IGG_HIP(hipGetLastError());
     return IGG_OK;
 }
 
 int launch_adjoint_boxes(int dtype, const AdjArgs &a, const Box *b, int nb, hipStream_t s)
 {
-    return dtype == IGG_F64 ? run_boxes<double>(a, b, nb, s) : run_boxes<float>(a, b, nb, s);
+    if (a.form == 1) return dtype == IGG_F64 ? run_boxes<double, 1>(a, b, nb, s) : run_boxes<float, 1>(a, b, nb, s);
+    return dtype == IGG_F64 ? run_boxes<double, 0>(a, b, nb, s) : run_boxes<float, 0>(a, b, nb, s);
 }
 
-template <typename C, int VEC, int BX, int TY, int RY>
+template <typename C, int VEC, int BX, int TY, int RY, int FORM>
 static int run_zmarch(const AdjArgs &a, const Box &b, hipStream_t s)
 {
     constexpr int TW = BX * VEC, TH = TY * RY;
@@ -323,9 +350,9 @@ static int run_zmarch(const AdjArgs &a, const Box &b, hipStream_t s)
     z.xh = a.xh;
     int64_t blocks = (int64_t)z.ntx * z.nty * ((depth + zc - 1) / zc);
     if (blocks == 0) return IGG_OK;
-    hipLaunchKernelGGL((k_adj_zmarch<C, VEC, BX, TY, RY>), dim3((unsigned)blocks), dim3(BX * TY), 0, s,
+    hipLaunchKernelGGL((k_adj_zmarch<C, VEC, BX, TY, RY, FORM>), dim3((unsigned)blocks), dim3(BX * TY), 0, s,
                        (C *)a.lam_n, (const C *)a.lp, (const C *)a.Tn, (const C *)a.Ci, (C *)a.gCi, z,
-                       (C)a.a, (C)a.rx, (C)a.ry, (C)a.rz);
+                       (C)a.a, (C)a.rx, (C)a.ry, (C)a.rz, (C)a.lamf);
     IGG_HIP(hipGetLastError());
     return IGG_OK;
 }
@@ -345,12 +372,20 @@ static bool vec2_ok(const AdjArgs &a)
 // 512-byte rows of 16 at 256^3 and 512^3 on MI355X.  FP32: 512-byte rows
 // (128 points) of 8.  One point per lane where the row length does not
 // allow 16-byte loads.
+template <int FORM>
+static int adjoint_inner(int dtype, const AdjArgs &a, const Box &b, hipStream_t s)
+{
+    if (dtype == IGG_F64)
+        return vec2_ok<double>(a) ? run_zmarch<double, 2, 64, 4, 1, FORM>(a, b, s)
+                                  : run_zmarch<double, 1, 64, 8, 2, FORM>(a, b, s);
+    return vec2_ok<float>(a) ? run_zmarch<float, 2, 64, 8, 1, FORM>(a, b, s)
+                             : run_zmarch<float, 1, 64, 8, 2, FORM>(a, b, s);
+}
+
 int launch_adjoint_inner(int dtype, const AdjArgs &a, const Box &b, hipStream_t s)
 {
     if (box_count(b) < zmarch_min_points()) return launch_adjoint_boxes(dtype, a, &b, 1, s);
-    if (dtype == IGG_F64)
-        return vec2_ok<double>(a) ? run_zmarch<double, 2, 64, 4, 1>(a, b, s) : run_zmarch<double, 1, 64, 8, 2>(a, b, s);
-    return vec2_ok<float>(a) ? run_zmarch<float, 2, 64, 8, 1>(a, b, s) : run_zmarch<float, 1, 64, 8, 2>(a, b, s);
+    return a.form == 1 ? adjoint_inner<1>(dtype, a, b, s) : adjoint_inner<0>(dtype, a, b, s);
 }
 
 }  // namespace igg

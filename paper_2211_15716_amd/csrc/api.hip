@@ -433,6 +433,56 @@ static int update_halo_ranks(const igg_field *fields, int nfields, void *stream)
     return launch_halo(fields, nfields, (hipStream_t)stream);
 }
 
+// The adjoint step of either form (0: Laplacian, 1: staggered flux form).
+static int adjoint_step(int form, const igg_field *lam_n, const igg_field *lam_np1, const igg_field *T_n,
+                        const igg_field *Ci, const igg_field *gCi, double lam, double dt, double dx, double dy,
+                        double dz, const int split[3], void *stream)
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    if (g.nranks > 1) return fail(IGG_ERR_STATE, "this entry point runs on a single-rank grid");
+    int rc;
+    if ((rc = check_field(lam_n, "lam_n", true))) return rc;
+    if ((rc = check_field(lam_np1, "lam_np1", true))) return rc;
+    if ((rc = check_field(T_n, "T_n", true))) return rc;
+    if ((rc = check_field(Ci, "Ci", true))) return rc;
+    if ((rc = check_field(gCi, "gCi", true))) return rc;
+    int dt_ = lam_n->dtype;
+    if (lam_np1->dtype != dt_ || T_n->dtype != dt_ || Ci->dtype != dt_ || gCi->dtype != dt_)
+        return fail(IGG_ERR_DTYPE, "adjoint fields must share one dtype");
+    if (dt_ == IGG_F16) return fail(IGG_ERR_DTYPE, "the adjoint runs in FP64 or FP32");
+    const igg_field *ins[3] = {lam_np1, T_n, Ci};
+    for (const igg_field *o : {lam_n, gCi})
+        for (const igg_field *i : ins)
+            if (overlaps_mem(*o, *i)) return fail(IGG_ERR_ALIAS, "an output shares memory with an input");
+    if (overlaps_mem(*lam_n, *gCi)) return fail(IGG_ERR_ALIAS, "lam_n shares memory with gCi");
+    if ((rc = check_spacings(lam, dt, dx, dy, dz))) return rc;
+    if ((rc = check_split(split, g.ol))) return rc;
+    if ((rc = ensure_device())) return rc;
+
+    hipStream_t s = (hipStream_t)stream;
+    // the x exchange of lam_n is stored by the adjoint kernels, as in the step
+    const int xon = (g.fuse_x && g.periods[0]) ? 1 : 0;
+    const XHalo xh{xon, xon, g.ol[0] - 1, g.n[0] - g.ol[0], 0, 0};
+    const int halo_dims = g.fuse_x ? 6 : 7;
+    AdjArgs a = form == 0 ? AdjArgs{lam_n->data, lam_np1->data, T_n->data, Ci->data, gCi->data, g.n[0], g.n[1],
+                                    g.n[2], dt * lam, 1.0 / (dx * dx), 1.0 / (dy * dy), 1.0 / (dz * dz), xh}
+                          : AdjArgs{lam_n->data, lam_np1->data, T_n->data, Ci->data, gCi->data, g.n[0], g.n[1],
+                                    g.n[2], dt, 1.0 / dx, 1.0 / dy, 1.0 / dz, xh, 1, lam};
+    if (!split) {
+        Box all{1, g.n[0] - 1, 1, g.n[1] - 1, 1, g.n[2] - 1};
+        if ((rc = timing_mark(s, 0))) return rc;
+        if ((rc = launch_adjoint_inner(dt_, a, all, s))) return rc;
+        if ((rc = timing_mark(s, 0))) return rc;
+        if (g.timing) { g.t_launches++; g.t_points += box_points(all); }
+        return launch_halo(lam_n, 1, s, halo_dims);
+    }
+    return run_split(
+        split, lam_n, 1, halo_dims,
+        [&](int, const Split &b, hipStream_t st) { return launch_adjoint_boxes(dt_, a, b.boundary, b.nb, st); },
+        [&](int, const Box &b, hipStream_t st) { return launch_adjoint_inner(dt_, a, b, st); }, s);
+}
+
 }  // namespace igg
 
 using namespace igg;
@@ -637,47 +687,7 @@ int diffusion_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1,
                            double lam, double dt, double dx, double dy, double dz,
                            const int split[3], void *stream)
 {
-    Grid &g = grid();
-    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
-    if (g.nranks > 1) return fail(IGG_ERR_STATE, "this entry point runs on a single-rank grid");
-    int rc;
-    if ((rc = check_field(lam_n, "lam_n", true))) return rc;
-    if ((rc = check_field(lam_np1, "lam_np1", true))) return rc;
-    if ((rc = check_field(T_n, "T_n", true))) return rc;
-    if ((rc = check_field(Ci, "Ci", true))) return rc;
-    if ((rc = check_field(gCi, "gCi", true))) return rc;
-    int dt_ = lam_n->dtype;
-    if (lam_np1->dtype != dt_ || T_n->dtype != dt_ || Ci->dtype != dt_ || gCi->dtype != dt_)
-        return fail(IGG_ERR_DTYPE, "adjoint fields must share one dtype");
-    if (dt_ == IGG_F16) return fail(IGG_ERR_DTYPE, "the adjoint runs in FP64 or FP32");
-    const igg_field *ins[3] = {lam_np1, T_n, Ci};
-    for (const igg_field *o : {lam_n, gCi})
-        for (const igg_field *i : ins)
-            if (overlaps_mem(*o, *i)) return fail(IGG_ERR_ALIAS, "an output shares memory with an input");
-    if (overlaps_mem(*lam_n, *gCi)) return fail(IGG_ERR_ALIAS, "lam_n shares memory with gCi");
-    if ((rc = check_spacings(lam, dt, dx, dy, dz))) return rc;
-    if ((rc = check_split(split, g.ol))) return rc;
-    if ((rc = ensure_device())) return rc;
-
-    hipStream_t s = (hipStream_t)stream;
-    // the x exchange of lam_n is stored by the adjoint kernels, as in the step
-    const int xon = (g.fuse_x && g.periods[0]) ? 1 : 0;
-    const XHalo xh{xon, xon, g.ol[0] - 1, g.n[0] - g.ol[0], 0, 0};
-    const int halo_dims = g.fuse_x ? 6 : 7;
-    AdjArgs a{lam_n->data, lam_np1->data, T_n->data, Ci->data, gCi->data, g.n[0], g.n[1], g.n[2],
-              dt * lam, 1.0 / (dx * dx), 1.0 / (dy * dy), 1.0 / (dz * dz), xh};
-    if (!split) {
-        Box all{1, g.n[0] - 1, 1, g.n[1] - 1, 1, g.n[2] - 1};
-        if ((rc = timing_mark(s, 0))) return rc;
-        if ((rc = launch_adjoint_inner(dt_, a, all, s))) return rc;
-        if ((rc = timing_mark(s, 0))) return rc;
-        if (g.timing) { g.t_launches++; g.t_points += box_points(all); }
-        return launch_halo(lam_n, 1, s, halo_dims);
-    }
-    return run_split(
-        split, lam_n, 1, halo_dims,
-        [&](int, const Split &b, hipStream_t st) { return launch_adjoint_boxes(dt_, a, b.boundary, b.nb, st); },
-        [&](int, const Box &b, hipStream_t st) { return launch_adjoint_inner(dt_, a, b, st); }, s);
+    return adjoint_step(0, lam_n, lam_np1, T_n, Ci, gCi, lam, dt, dx, dy, dz, split, stream);
 }
 
 static int check_face(const igg_field *q, const char *name, int dim)
@@ -745,46 +755,11 @@ int diffusion_flux_step(const igg_field *T2, const igg_field *T, const igg_field
         [&](int, const Box &b, hipStream_t st) { return launch_flux_inner(ty, a, b, st); }, s);
 }
 
-int diffusion_flux_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1,
-                                const igg_field *Ci, const igg_field *qx, const igg_field *qy,
-                                const igg_field *qz, const igg_field *px, const igg_field *py,
-                                const igg_field *pz, const igg_field *gCi, double lam, double dt,
-                                double dx, double dy, double dz, void *stream)
+int diffusion_flux_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1, const igg_field *T_n,
+                                const igg_field *Ci, const igg_field *gCi, double lam, double dt, double dx,
+                                double dy, double dz, const int split[3], void *stream)
 {
-    Grid &g = grid();
-    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
-    if (g.nranks > 1) return fail(IGG_ERR_STATE, "this entry point runs on a single-rank grid");
-    int rc;
-    if ((rc = check_field(lam_n, "lam_n", true))) return rc;
-    if ((rc = check_field(lam_np1, "lam_np1", true))) return rc;
-    if ((rc = check_field(Ci, "Ci", true))) return rc;
-    if ((rc = check_field(gCi, "gCi", true))) return rc;
-    if ((rc = check_face(qx, "qx", 0))) return rc;
-    if ((rc = check_face(qy, "qy", 1))) return rc;
-    if ((rc = check_face(qz, "qz", 2))) return rc;
-    if ((rc = check_face(px, "px", 0))) return rc;
-    if ((rc = check_face(py, "py", 1))) return rc;
-    if ((rc = check_face(pz, "pz", 2))) return rc;
-    int ty = lam_n->dtype;
-    for (const igg_field *f : {lam_np1, Ci, gCi, qx, qy, qz, px, py, pz})
-        if (f->dtype != ty) return fail(IGG_ERR_DTYPE, "flux-form adjoint fields must share one dtype");
-    if (ty == IGG_F16) return fail(IGG_ERR_DTYPE, "the flux form runs in FP64 or FP32");
-    const igg_field *outs[5] = {lam_n, gCi, px, py, pz};
-    const igg_field *ins[5] = {lam_np1, Ci, qx, qy, qz};
-    for (int o = 0; o < 5; ++o) {
-        for (int i = 0; i < 5; ++i)
-            if (overlaps_mem(*outs[o], *ins[i])) return fail(IGG_ERR_ALIAS, "an output shares memory with an input");
-        for (int p = 0; p < o; ++p)
-            if (overlaps_mem(*outs[o], *outs[p])) return fail(IGG_ERR_ALIAS, "outputs share memory");
-    }
-    if ((rc = check_spacings(lam, dt, dx, dy, dz))) return rc;
-    if ((rc = ensure_device())) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    FluxAdjArgs a{lam_n->data, lam_np1->data, Ci->data, qx->data, qy->data, qz->data,
-                  px->data, py->data, pz->data, gCi->data, g.n[0], g.n[1], g.n[2],
-                  lam, dt, 1.0 / dx, 1.0 / dy, 1.0 / dz};
-    if ((rc = launch_flux_adjoint(ty, a, s))) return rc;
-    return launch_halo(lam_n, 1, s);
+    return adjoint_step(1, lam_n, lam_np1, T_n, Ci, gCi, lam, dt, dx, dy, dz, split, stream);
 }
 
 int igg_reduce(int op, const igg_field *a, const igg_field *b, double *out, void *stream)

@@ -51,6 +51,21 @@ __device__ __forceinline__ C laplace(C c, C xm, C xp, C ym, C yp, C zm, C zp, C 
     return fma_(d2z, rz, fma_(d2y, ry, d2x * rx));
 }
 
+// Face flux of the staggered form: q = -lam*(hi - lo)*rd for the cells on
+// either side of the face, rd = 1/dd.
+template <typename C>
+__device__ __forceinline__ C face_flux(C hi, C lo, C lam, C rd)
+{
+    return -lam * ((hi - lo) * rd);
+}
+
+// Divergence of a cell's six face fluxes (lower l, upper u per dimension).
+template <typename C>
+__device__ __forceinline__ C flux_div(C qxl, C qxu, C qyl, C qyu, C qzl, C qzu, C rdx, C rdy, C rdz)
+{
+    return ((qxu - qxl) * rdx + (qyu - qyl) * rdy) + (qzu - qzl) * rdz;
+}
+
 // ------------------------------------------------------------------ hash
 // PCG hash of Jarzynski and Olano, "Hash Functions for GPU Rendering",
 // JCGT 9(3), 2020: one LCG step of O'Neill's PCG followed by its RXS-M-XS

@@ -1,6 +1,7 @@
 // flux.hip -- staggered-grid flux form of the diffusion step (Sec. 2 on the
-// regular staggered grid): face fluxes q = -lam*grad(T), then the cell
-// update T2 = T - dt*Ci*div(q), and the adjoint of that pair.
+// regular staggered grid): face fluxes q = -lam*grad(T) and the cell update
+// T2 = T - dt*Ci*div(q), in one pass per cell.  Its adjoint runs in
+// adjoint.hip (the same kernels as the Laplacian form's adjoint).
 //
 // Sizes: cells (nx,ny,nz); qx (nx+1,ny,nz), qy (nx,ny+1,nz), qz (nx,ny,nz+1).
 // Face f of a dimension lies between cells f-1 and f; fluxes are computed on
@@ -11,86 +12,10 @@
 
 namespace igg {
 
-// Face field geometry for component d: extent of computed faces and strides.
+// Cell grid size (the face fields add one point in their own dimension).
 struct FaceGeom {
     int nx, ny, nz;
 };
-
-template <typename C>
-__device__ __forceinline__ bool face_index(int d, int64_t t, const FaceGeom &g, int &i, int &j, int &k)
-{
-    // computed faces: along d: 1..n_d-1 (n_d-1 faces); others: 1..n-2
-    const int ex = d == 0 ? g.nx - 1 : g.nx - 2;
-    const int ey = d == 1 ? g.ny - 1 : g.ny - 2;
-    const int ez = d == 2 ? g.nz - 1 : g.nz - 2;
-    if (t >= (int64_t)ex * ey * ez) return false;
-    i = 1 + (int)(t % ex);
-    int64_t r = t / ex;
-    j = 1 + (int)(r % ey);
-    k = 1 + (int)(r / ey);
-    return true;
-}
-
-// q_d[f] = -lam*(V[f]-V[f-1])*rd for the cell field V (blockIdx.y = d).
-// With mu_ci != null the cell field is mu = mu_ci .* V (the adjoint flux).
-template <typename C>
-__global__ void __launch_bounds__(256)
-k_flux(C *__restrict__ qx, C *__restrict__ qy, C *__restrict__ qz, const C *__restrict__ V,
-       const C *__restrict__ mu_ci, FaceGeom g, C lam, C rdx, C rdy, C rdz)
-{
-    const int d = blockIdx.y;
-    int i, j, k;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (!face_index<C>(d, t, g, i, j, k)) return;
-    const int64_t cs = (d == 0) ? 1 : (d == 1) ? (int64_t)g.nx : (int64_t)g.nx * g.ny;
-    const int64_t pc = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
-    C hi = V[pc], lo = V[pc - cs];
-    if (mu_ci) {
-        hi = mu_ci[pc] * hi;
-        lo = mu_ci[pc - cs] * lo;
-    }
-    const C rd = d == 0 ? rdx : d == 1 ? rdy : rdz;
-    const C v = -lam * ((hi - lo) * rd);
-    if (d == 0)
-        qx[i + (int64_t)(g.nx + 1) * (j + (int64_t)g.ny * k)] = v;
-    else if (d == 1)
-        qy[i + (int64_t)g.nx * (j + (int64_t)(g.ny + 1) * k)] = v;
-    else
-        qz[i + (int64_t)g.nx * (j + (int64_t)g.ny * k)] = v;
-}
-
-template <typename C>
-__device__ __forceinline__ C divergence(const C *qx, const C *qy, const C *qz, int i, int j, int k,
-                                        const FaceGeom &g, C rdx, C rdy, C rdz)
-{
-    const int64_t px = i + (int64_t)(g.nx + 1) * (j + (int64_t)g.ny * k);
-    const int64_t py = i + (int64_t)g.nx * (j + (int64_t)(g.ny + 1) * k);
-    const int64_t pz = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
-    const C dqx = (qx[px + 1] - qx[px]) * rdx;
-    const C dqy = (qy[py + g.nx] - qy[py]) * rdy;
-    const C dqz = (qz[pz + (int64_t)g.nx * g.ny] - qz[pz]) * rdz;
-    return (dqx + dqy) + dqz;
-}
-
-// lam_n = lp - dt*div(p), gCi += -dt*lp*div(q) on inner cells.
-template <typename C>
-__global__ void __launch_bounds__(256)
-k_flux_adj_update(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restrict__ px,
-                  const C *__restrict__ py, const C *__restrict__ pz, const C *__restrict__ qx,
-                  const C *__restrict__ qy, const C *__restrict__ qz, C *__restrict__ gCi, FaceGeom g, C dt,
-                  C rdx, C rdy, C rdz)
-{
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int ex = g.nx - 2, ey = g.ny - 2;
-    if (t >= (int64_t)ex * ey * (g.nz - 2)) return;
-    const int i = 1 + (int)(t % ex);
-    const int64_t r = t / ex;
-    const int j = 1 + (int)(r % ey), k = 1 + (int)(r / ey);
-    const int64_t p = i + (int64_t)g.nx * (j + (int64_t)g.ny * k);
-    const C l = lp[p];
-    lam_n[p] = fma_(-dt, divergence<C>(px, py, pz, i, j, k, g, rdx, rdy, rdz), l);
-    gCi[p] = fma_(-dt * l, divergence<C>(qx, qy, qz, i, j, k, g, rdx, rdy, rdz), gCi[p]);
-}
 
 static unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
@@ -99,8 +24,9 @@ static unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 // upper face where the cell is the last of its row, column or plane), the
 // update T2 = T - dt*Ci*div(q) from the cell's six faces, and the x
 // exchange of all four fields when x is periodic on this single rank.  The
-// faces come from the same expression as in k_flux and the divergence sums
-// in the same order, so every value equals the two-pass form's.
+// faces come from one expression (face_flux) and the divergence sums in a
+// fixed order (flux_div), so every value equals a face pass followed by a
+// cell pass.
 //
 // x exchange (this process its own x neighbour): T2, qy and qz (nx points
 // in x, overlap ol) copy column ol-1 to nx-1 and nx-ol to 0; qx (nx+1
@@ -108,18 +34,6 @@ static unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 struct FluxXH {
     int on, ol;
 };
-
-template <typename C>
-__device__ __forceinline__ C face_flux(C hi, C lo, C lam, C rd)
-{
-    return -lam * ((hi - lo) * rd);
-}
-
-template <typename C>
-__device__ __forceinline__ C flux_div(C qxl, C qxu, C qyl, C qyu, C qzl, C qzu, C rdx, C rdy, C rdz)
-{
-    return ((qxu - qxl) * rdx + (qyu - qyl) * rdy) + (qzu - qzl) * rdz;
-}
 
 // Stores of one cell that are not plain per-cell stores: the upper faces at
 // the ends and the x-exchange copies.  p: the cell's offset in a cell-sized
@@ -448,30 +362,6 @@ int launch_flux_inner(int dtype, const FluxArgs &a, const Box &b, hipStream_t s)
                                   : run_fused_zmarch<double, 1, 64, 4, 2>(a, b, s);
     return flux_vec_ok(a, 4) ? run_fused_zmarch<float, 4, 64, 4, 2>(a, b, s)
                               : run_fused_zmarch<float, 1, 64, 4, 2>(a, b, s);
-}
-
-template <typename C>
-static int run_adj(const FluxAdjArgs &a, hipStream_t s)
-{
-    FaceGeom g{a.nx, a.ny, a.nz};
-    int64_t most = (int64_t)(a.nx - 1) * (a.ny - 1) * (a.nz - 1);
-    // adjoint fluxes of mu = Ci .* lp
-    hipLaunchKernelGGL(k_flux<C>, dim3(blocks_for(most), 3), dim3(256), 0, s, (C *)a.px, (C *)a.py,
-                       (C *)a.pz, (const C *)a.lp, (const C *)a.Ci, g, (C)a.lam, (C)a.rdx, (C)a.rdy,
-                       (C)a.rdz);
-    IGG_HIP(hipGetLastError());
-    int64_t n = (int64_t)(a.nx - 2) * (a.ny - 2) * (a.nz - 2);
-    hipLaunchKernelGGL(k_flux_adj_update<C>, dim3(blocks_for(n)), dim3(256), 0, s, (C *)a.lam_n,
-                       (const C *)a.lp, (const C *)a.px, (const C *)a.py, (const C *)a.pz, (const C *)a.qx,
-                       (const C *)a.qy, (const C *)a.qz, (C *)a.gCi, g, (C)a.dt, (C)a.rdx, (C)a.rdy,
-                       (C)a.rdz);
-    IGG_HIP(hipGetLastError());
-    return IGG_OK;
-}
-
-int launch_flux_adjoint(int dtype, const FluxAdjArgs &a, hipStream_t s)
-{
-    return dtype == IGG_F64 ? run_adj<double>(a, s) : run_adj<float>(a, s);
 }
 
 }  // namespace igg

@@ -154,8 +154,10 @@ struct AdjArgs {
     const void *Ci;
     void *gCi;
     int nx, ny, nz;
-    double a, rx, ry, rz;
-    XHalo xh;  // x exchange of lam_n fused into the stores
+    double a, rx, ry, rz;  // Laplacian form: dt*lam, 1/dd^2; flux form: dt, 1/dd
+    XHalo xh;              // x exchange of lam_n fused into the stores
+    int form = 0;          // 0: Laplacian step, 1: staggered flux form
+    double lamf = 0.0;     // lam, for the flux form's face fluxes
 };
 int launch_adjoint_boxes(int dtype, const AdjArgs &a, const Box *b, int nb, hipStream_t s);
 int launch_adjoint_inner(int dtype, const AdjArgs &a, const Box &b, hipStream_t s);
@@ -175,17 +177,6 @@ struct FluxArgs {
 int launch_flux_boxes(int dtype, const FluxArgs &a, const Box *b, int nb, hipStream_t s);
 int launch_flux_inner(int dtype, const FluxArgs &a, const Box &b, hipStream_t s);
 
-struct FluxAdjArgs {
-    void *lam_n;
-    const void *lp;
-    const void *Ci;
-    const void *qx, *qy, *qz;
-    void *px, *py, *pz;
-    void *gCi;
-    int nx, ny, nz;
-    double lam, dt, rdx, rdy, rdz;
-};
-int launch_flux_adjoint(int dtype, const FluxAdjArgs &a, hipStream_t s);
 
 int launch_reduce(int op, const igg_field &a, const igg_field *b, double *out, hipStream_t s);
 

@@ -71,27 +71,25 @@ class Problem:
 class FluxProblem:
     """The staggered flux form of the same time loop (Sec. 2 staggered grid)
     behind the interface Sweep uses: step(out, T, Ci) runs
-    diffusion_flux_step with the face fluxes in work arrays, and
-    adjoint(lam_n, lam_np1, Tn, Ci, gCi) first recomputes the fluxes of step
-    n from the state Tn (one more flux step into scratch), then runs
-    diffusion_flux_step_adjoint.  The fluxes and their adjoints live in six
-    face-sized work arrays of T's dtype, made on first use."""
+    diffusion_flux_step with the face fluxes in work arrays (made on first
+    use; `fluxes` holds the last step's), and adjoint(lam_n, lam_np1, Tn,
+    Ci, gCi) runs diffusion_flux_step_adjoint, which forms the fluxes of
+    step n from the state Tn."""
 
     def __init__(self, lam, dt, dx, dy, dz, split=None):
         self.lam, self.dt, self.dx, self.dy, self.dz = lam, dt, dx, dy, dz
         self.split = split
-        self._q = self._p = self._scratch = None
+        self._q = None
 
     def _faces(self, T):
         if self._q is None:
             nz, ny, nx = T.shape
             shapes = [(nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx)]
             self._q = [torch.zeros(s, dtype=T.dtype, device=T.device) for s in shapes]
-            self._p = [torch.zeros(s, dtype=T.dtype, device=T.device) for s in shapes]
-        return self._q, self._p
+        return self._q
 
     def step(self, out, T, Ci, stream=None):
-        q, _ = self._faces(T)
+        q = self._faces(T)
         igg.diffusion_flux_step(out, T, Ci, *q, self.lam, self.dt, self.dx, self.dy, self.dz, split=self.split,
                                 stream=stream)
 
@@ -101,12 +99,8 @@ class FluxProblem:
         return self._q
 
     def adjoint(self, lam_n, lam_np1, Tn, Ci, gCi, stream=None):
-        q, pf = self._faces(Tn)
-        if self._scratch is None:
-            self._scratch = Tn.clone()  # keeps the non-periodic halo planes
-        self.step(self._scratch, Tn, Ci, stream=stream)
-        igg.diffusion_flux_step_adjoint(lam_n, lam_np1, Ci, *q, *pf, gCi, self.lam, self.dt, self.dx, self.dy,
-                                        self.dz, stream=stream)
+        igg.diffusion_flux_step_adjoint(lam_n, lam_np1, Tn, Ci, gCi, self.lam, self.dt, self.dx, self.dy, self.dz,
+                                        split=self.split, stream=stream)
 
 
 class Sweep:

@@ -84,7 +84,7 @@ def load():
     lib.diffusion_dt.argtypes = [_PF, d, d, d, d, ctypes.POINTER(d), vp]
     lib.diffusion_step_adjoint.argtypes = [_PF] * 5 + [d] * 5 + [_PI, vp]
     lib.diffusion_flux_step.argtypes = [_PF] * 6 + [d] * 5 + [_PI, vp]
-    lib.diffusion_flux_step_adjoint.argtypes = [_PF] * 10 + [d] * 5 + [vp]
+    lib.diffusion_flux_step_adjoint.argtypes = [_PF] * 5 + [d] * 5 + [_PI, vp]
     lib.igg_reduce.argtypes = [ctypes.c_int, _PF, _PF, ctypes.POINTER(d), vp]
     lib.igg_plan_split.argtypes = [_PI, _PI, (ctypes.c_int * 6) * 7, _PI]
     lib.igg_timing_enable.argtypes = [ctypes.c_int]
@@ -254,11 +254,12 @@ def diffusion_flux_step(T2, T, Ci, qx, qy, qz, lam, dt, dx, dy, dz, split=None, 
                                       float(dy), float(dz), _int3(split), _stream(stream)))
 
 
-def diffusion_flux_step_adjoint(lam_n, lam_np1, Ci, qx, qy, qz, px, py, pz, gCi, lam, dt, dx, dy, dz,
-                                stream=None):
-    fs = [field(t) for t in (lam_n, lam_np1, Ci, qx, qy, qz, px, py, pz, gCi)]
-    _check(load().diffusion_flux_step_adjoint(*[ctypes.byref(f) for f in fs], float(lam), float(dt),
-                                              float(dx), float(dy), float(dz), _stream(stream)))
+def diffusion_flux_step_adjoint(lam_n, lam_np1, T_n, Ci, gCi, lam, dt, dx, dy, dz, split=None, stream=None):
+    """Adjoint of the flux-form step n: lam_n from lam_np1 (valid halo), gCi
+    accumulated; the fluxes of step n are formed from T_n."""
+    fs = [field(t) for t in (lam_n, lam_np1, T_n, Ci, gCi)]
+    _check(load().diffusion_flux_step_adjoint(*[ctypes.byref(f) for f in fs], float(lam), float(dt), float(dx),
+                                              float(dy), float(dz), _int3(split), _stream(stream)))
 
 
 # ------------------------------------------------------------------ reductions and helpers

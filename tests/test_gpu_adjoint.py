@@ -267,10 +267,10 @@ def test_fp32_adjoint_close_to_fp64():
 
 
 def test_flux_form_checkpointed_adjoint_matches_oracle():
-    """The flux form through the checkpointed sweep (fluxes recomputed from
-    the stored or recomputed states): every schedule gives the store-all
-    loss and gradients bit for bit, and they match the oracle's flux-form
-    gradient."""
+    """The flux form through the checkpointed sweep (the adjoint forms the
+    fluxes from the stored or recomputed states): every schedule and split
+    gives the store-all loss and gradients bit for bit, and they match the
+    oracle's flux-form gradient."""
     say("flux checkpointed adjoint")
     n = (34, 28, 24)
     nx, ny, nz = n
@@ -282,13 +282,14 @@ def test_flux_form_checkpointed_adjoint_matches_oracle():
     nt = 11
     L_ref, gT_ref, gC_ref = oracle.flux_gradient(T0, Ci, Tobs, nt, 1.0, dt, *d)
     with grid(n):
-        prob = diffusion.FluxProblem(1.0, dt, *d)
         res = {}
-        for sched in [("store_all",), ("sqrt",), ("periodic", 4), ("binomial", 3)]:
-            L, gT, gC, sw = diffusion.loss_and_grad(dev(T0), dev(Ci), dev(Tobs), prob, nt, sched)
-            res[sched] = (L, host(gT), host(gC))
-            assert sw.adjoints == nt
-    L0, gT0, gC0 = res[("store_all",)]
+        for split in (None, (16, 3, 3)):
+            prob = diffusion.FluxProblem(1.0, dt, *d, split=split)
+            for sched in [("store_all",), ("sqrt",), ("periodic", 4), ("binomial", 3)]:
+                L, gT, gC, sw = diffusion.loss_and_grad(dev(T0), dev(Ci), dev(Tobs), prob, nt, sched)
+                res[(split,) + sched] = (L, host(gT), host(gC))
+                assert sw.adjoints == nt
+    L0, gT0, gC0 = res[(None, "store_all")]
     for sched, (L, gT, gC) in res.items():
         assert L == L0 and np.array_equal(gT, gT0) and np.array_equal(gC, gC0), sched
     assert abs(L0 - L_ref) <= 1e-12 * L_ref
