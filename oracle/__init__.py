@@ -17,9 +17,11 @@ paper's ``@inn``).  With one process and a periodic dimension the inner
 points are the unique points of the global grid.
 
 Readings of the paper that this module fixes (the paper is silent on them):
-  * the halo update sends plane ol-1 to the upper neighbour's plane n-1 and
-    plane n-ol to the lower neighbour's plane 0, dimensions in order x, y, z,
-    full planes (edges and corners become images in every dimension);
+  * the halo update sends plane ol-1 to the lower neighbour's plane n-1 and
+    plane n-ol to the upper neighbour's plane 0 (neighbours share ol planes,
+    so those are the same global planes), dimensions in order x, y, z, full
+    planes (edges and corners become images in every dimension); with one
+    periodic process both neighbours are the process itself;
   * the global grid size per dimension is dims*(n-ol) + ol*(1-period);
   * a field one point larger than the grid in a dimension (a staggered face
     field) has overlap ol+1 in that dimension.
