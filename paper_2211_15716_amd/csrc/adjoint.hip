@@ -359,25 +359,27 @@ static int run_zmarch(const AdjArgs &a, const Box &b, hipStream_t s)
 
 static bool aligned(const void *p, int bytes) { return ((uintptr_t)p % (uintptr_t)bytes) == 0; }
 
-template <typename C>
+template <typename C, int VEC = 2>
 static bool vec2_ok(const AdjArgs &a)
 {
-    const int vb = 2 * (int)sizeof(C);
-    return a.nx % 2 == 0 && aligned(a.lam_n, vb) && aligned(a.lp, vb) && aligned(a.Tn, vb) &&
+    const int vb = VEC * (int)sizeof(C);
+    return a.nx % VEC == 0 && aligned(a.lam_n, vb) && aligned(a.lp, vb) && aligned(a.Tn, vb) &&
            aligned(a.Ci, vb) && aligned(a.gCi, vb);
 }
 
-// FP64: 1 KB tile rows (128 points) of 4 rows, 256 threads, one row per
-// thread (the two staged fields need many registers): 10% faster than
-// 512-byte rows of 16 at 256^3 and 512^3 on MI355X.  FP32: 512-byte rows
-// (128 points) of 8.  One point per lane where the row length does not
-// allow 16-byte loads.
+// 1 KB tile rows of 4 rows, 256 threads, one row per thread (the two
+// staged fields need many registers), 16-byte loads: FP64 128 points per
+// row (10% faster than 512-byte rows of 16 at 256^3 and 512^3 on MI355X),
+// FP32 256 points (24% faster than 8-byte loads on 512-byte rows at 512^3
+// and 768^3).  Narrower vectors, then one point per lane, where the row
+// length or alignment does not allow 16-byte loads.
 template <int FORM>
 static int adjoint_inner(int dtype, const AdjArgs &a, const Box &b, hipStream_t s)
 {
     if (dtype == IGG_F64)
         return vec2_ok<double>(a) ? run_zmarch<double, 2, 64, 4, 1, FORM>(a, b, s)
                                   : run_zmarch<double, 1, 64, 8, 2, FORM>(a, b, s);
+    if (vec2_ok<float, 4>(a)) return run_zmarch<float, 4, 64, 4, 1, FORM>(a, b, s);
     return vec2_ok<float>(a) ? run_zmarch<float, 2, 64, 8, 1, FORM>(a, b, s)
                              : run_zmarch<float, 1, 64, 8, 2, FORM>(a, b, s);
 }

@@ -257,13 +257,16 @@ def test_fp32_adjoint_close_to_fp64():
     dx = 1 / 39
     dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
     with grid(n):
-        prob = diffusion.Problem(1.0, dt, dx, dx, dx)
-        r64 = diffusion.loss_and_grad(dev(T0), dev(Ci), dev(Tobs), prob, nt)
-        r32 = diffusion.loss_and_grad(dev(T0, torch.float32), dev(Ci, torch.float32), dev(Tobs, torch.float32),
-                                      prob, nt)
-        for a, b in ((r64[1], r32[1]), (r64[2], r32[2])):
-            err = torch.max(torch.abs(a - b.double())).item() / torch.max(torch.abs(a)).item()
-            assert err <= 1e-5, err
+        for prob in (diffusion.Problem(1.0, dt, dx, dx, dx), diffusion.FluxProblem(1.0, dt, dx, dx, dx),
+                     diffusion.FluxProblem(1.0, dt, dx, dx, dx, split=(16, 3, 3))):
+            say("fp32 adjoint", type(prob).__name__, prob.split)
+            r64 = diffusion.loss_and_grad(dev(T0), dev(Ci), dev(Tobs), prob, nt)
+            prob32 = type(prob)(1.0, dt, dx, dx, dx, split=prob.split)
+            r32 = diffusion.loss_and_grad(dev(T0, torch.float32), dev(Ci, torch.float32),
+                                          dev(Tobs, torch.float32), prob32, nt)
+            for a, b in ((r64[1], r32[1]), (r64[2], r32[2])):
+                err = torch.max(torch.abs(a - b.double())).item() / torch.max(torch.abs(a)).item()
+                assert err <= 1e-5, err
 
 
 def test_flux_form_checkpointed_adjoint_matches_oracle():
