@@ -230,6 +230,16 @@ int diffusion_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1,
                            double lam, double dt, double dx, double dy, double dz,
                            const int split[3], void *stream);
 
+/* diffusion_step_adjoint for every rank of the grid: each argument is an
+ * array of nranks fields, rank r's blocks (no output block sharing memory
+ * with another block).  The x exchange of lam_n stores into the x
+ * neighbours' blocks and one igg_update_halo_ranks of lam_n follows, so the
+ * result equals the adjoint step on one block of the global grid bit for
+ * bit.  Errors: as diffusion_step_adjoint, naming the rank. */
+int diffusion_step_adjoint_ranks(const igg_field *lam_n, const igg_field *lam_np1, const igg_field *T_n,
+                                 const igg_field *Ci, const igg_field *gCi, double lam, double dt, double dx,
+                                 double dy, double dz, const int split[3], void *stream);
+
 /* ---------------------------------------------- staggered flux form */
 
 /* Flux form of the same step on the staggered grid (Sec. 2 "regular

@@ -433,54 +433,79 @@ static int update_halo_ranks(const igg_field *fields, int nfields, void *stream)
     return launch_halo(fields, nfields, (hipStream_t)stream);
 }
 
-// The adjoint step of either form (0: Laplacian, 1: staggered flux form).
+// The adjoint step of either form (0: Laplacian, 1: staggered flux form)
+// for the grid's nranks ranks: each argument is an array of one field per
+// rank (a single field on a one-rank grid).
 static int adjoint_step(int form, const igg_field *lam_n, const igg_field *lam_np1, const igg_field *T_n,
                         const igg_field *Ci, const igg_field *gCi, double lam, double dt, double dx, double dy,
                         double dz, const int split[3], void *stream)
 {
     Grid &g = grid();
-    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
-    if (g.nranks > 1) return fail(IGG_ERR_STATE, "this entry point runs on a single-rank grid");
     int rc;
-    if ((rc = check_field(lam_n, "lam_n", true))) return rc;
-    if ((rc = check_field(lam_np1, "lam_np1", true))) return rc;
-    if ((rc = check_field(T_n, "T_n", true))) return rc;
-    if ((rc = check_field(Ci, "Ci", true))) return rc;
-    if ((rc = check_field(gCi, "gCi", true))) return rc;
-    int dt_ = lam_n->dtype;
-    if (lam_np1->dtype != dt_ || T_n->dtype != dt_ || Ci->dtype != dt_ || gCi->dtype != dt_)
-        return fail(IGG_ERR_DTYPE, "adjoint fields must share one dtype");
+    const int P = g.nranks;
+    if (!lam_n || !lam_np1 || !T_n || !Ci || !gCi) return fail(IGG_ERR_ARG, "null field");
+    const int dt_ = lam_n[0].dtype;
+    for (int r = 0; r < P; ++r) {
+        const std::string sfx = P > 1 ? "[" + std::to_string(r) + "]" : "";
+        if ((rc = check_field(&lam_n[r], ("lam_n" + sfx).c_str(), true))) return rc;
+        if ((rc = check_field(&lam_np1[r], ("lam_np1" + sfx).c_str(), true))) return rc;
+        if ((rc = check_field(&T_n[r], ("T_n" + sfx).c_str(), true))) return rc;
+        if ((rc = check_field(&Ci[r], ("Ci" + sfx).c_str(), true))) return rc;
+        if ((rc = check_field(&gCi[r], ("gCi" + sfx).c_str(), true))) return rc;
+        if (lam_n[r].dtype != dt_ || lam_np1[r].dtype != dt_ || T_n[r].dtype != dt_ || Ci[r].dtype != dt_ ||
+            gCi[r].dtype != dt_)
+            return fail(IGG_ERR_DTYPE, "adjoint fields must share one dtype");
+    }
     if (dt_ == IGG_F16) return fail(IGG_ERR_DTYPE, "the adjoint runs in FP64 or FP32");
-    const igg_field *ins[3] = {lam_np1, T_n, Ci};
-    for (const igg_field *o : {lam_n, gCi})
-        for (const igg_field *i : ins)
-            if (overlaps_mem(*o, *i)) return fail(IGG_ERR_ALIAS, "an output shares memory with an input");
-    if (overlaps_mem(*lam_n, *gCi)) return fail(IGG_ERR_ALIAS, "lam_n shares memory with gCi");
+    for (int r = 0; r < P; ++r)
+        for (int q = 0; q < P; ++q) {
+            for (const igg_field *o : {&lam_n[r], &gCi[r]})
+                for (const igg_field *i : {&lam_np1[q], &T_n[q], &Ci[q]})
+                    if (overlaps_mem(*o, *i)) return fail(IGG_ERR_ALIAS, "an output shares memory with an input");
+            if (overlaps_mem(lam_n[r], gCi[q])) return fail(IGG_ERR_ALIAS, "lam_n shares memory with gCi");
+            if (q != r && (overlaps_mem(lam_n[r], lam_n[q]) || overlaps_mem(gCi[r], gCi[q])))
+                return fail(IGG_ERR_ALIAS, "two ranks' outputs share memory");
+        }
     if ((rc = check_spacings(lam, dt, dx, dy, dz))) return rc;
     if ((rc = check_split(split, g.ol))) return rc;
+    // per rank: the x exchange of lam_n stored by the adjoint kernels into
+    // the x neighbours' lam_n, as in the step
+    std::vector<AdjArgs> args(P);
+    const int64_t esz = elem_bytes(dt_);
+    for (int r = 0; r < P; ++r) {
+        XHalo xh{0, 0, g.ol[0] - 1, g.n[0] - g.ol[0], 0, 0};
+        if (g.fuse_x)
+            for (int side = 0; side < 2; ++side) {
+                const int q = rank_neighbor(r, 0, side);
+                if (q < 0) continue;
+                const int64_t diff = (int64_t)((intptr_t)lam_n[q].data - (intptr_t)lam_n[r].data);
+                if (diff % esz) return fail(IGG_ERR_ARG, "lam_n blocks must be aligned to their element size");
+                (side == 0 ? xh.on_lo : xh.on_hi) = 1;
+                (side == 0 ? xh.d_lo : xh.d_hi) = diff / esz;
+            }
+        args[r] = form == 0 ? AdjArgs{lam_n[r].data, lam_np1[r].data, T_n[r].data, Ci[r].data, gCi[r].data, g.n[0],
+                                      g.n[1], g.n[2], dt * lam, 1.0 / (dx * dx), 1.0 / (dy * dy), 1.0 / (dz * dz),
+                                      xh}
+                            : AdjArgs{lam_n[r].data, lam_np1[r].data, T_n[r].data, Ci[r].data, gCi[r].data, g.n[0],
+                                      g.n[1], g.n[2], dt, 1.0 / dx, 1.0 / dy, 1.0 / dz, xh, 1, lam};
+    }
     if ((rc = ensure_device())) return rc;
-
     hipStream_t s = (hipStream_t)stream;
-    // the x exchange of lam_n is stored by the adjoint kernels, as in the step
-    const int xon = (g.fuse_x && g.periods[0]) ? 1 : 0;
-    const XHalo xh{xon, xon, g.ol[0] - 1, g.n[0] - g.ol[0], 0, 0};
     const int halo_dims = g.fuse_x ? 6 : 7;
-    AdjArgs a = form == 0 ? AdjArgs{lam_n->data, lam_np1->data, T_n->data, Ci->data, gCi->data, g.n[0], g.n[1],
-                                    g.n[2], dt * lam, 1.0 / (dx * dx), 1.0 / (dy * dy), 1.0 / (dz * dz), xh}
-                          : AdjArgs{lam_n->data, lam_np1->data, T_n->data, Ci->data, gCi->data, g.n[0], g.n[1],
-                                    g.n[2], dt, 1.0 / dx, 1.0 / dy, 1.0 / dz, xh, 1, lam};
     if (!split) {
         Box all{1, g.n[0] - 1, 1, g.n[1] - 1, 1, g.n[2] - 1};
-        if ((rc = timing_mark(s, 0))) return rc;
-        if ((rc = launch_adjoint_inner(dt_, a, all, s))) return rc;
-        if ((rc = timing_mark(s, 0))) return rc;
-        if (g.timing) { g.t_launches++; g.t_points += box_points(all); }
+        for (int r = 0; r < P; ++r) {
+            if ((rc = timing_mark(s, 0))) return rc;
+            if ((rc = launch_adjoint_inner(dt_, args[r], all, s))) return rc;
+            if ((rc = timing_mark(s, 0))) return rc;
+            if (g.timing) { g.t_launches++; g.t_points += box_points(all); }
+        }
         return launch_halo(lam_n, 1, s, halo_dims);
     }
     return run_split(
         split, lam_n, 1, halo_dims,
-        [&](int, const Split &b, hipStream_t st) { return launch_adjoint_boxes(dt_, a, b.boundary, b.nb, st); },
-        [&](int, const Box &b, hipStream_t st) { return launch_adjoint_inner(dt_, a, b, st); }, s);
+        [&](int r, const Split &b, hipStream_t st) { return launch_adjoint_boxes(dt_, args[r], b.boundary, b.nb, st); },
+        [&](int r, const Box &b, hipStream_t st) { return launch_adjoint_inner(dt_, args[r], b, st); }, s);
 }
 
 }  // namespace igg
@@ -687,6 +712,19 @@ int diffusion_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1,
                            double lam, double dt, double dx, double dy, double dz,
                            const int split[3], void *stream)
 {
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    if (g.nranks > 1)
+        return fail(IGG_ERR_STATE, "the grid holds several virtual ranks: use diffusion_step_adjoint_ranks");
+    return adjoint_step(0, lam_n, lam_np1, T_n, Ci, gCi, lam, dt, dx, dy, dz, split, stream);
+}
+
+int diffusion_step_adjoint_ranks(const igg_field *lam_n, const igg_field *lam_np1, const igg_field *T_n,
+                                 const igg_field *Ci, const igg_field *gCi, double lam, double dt, double dx,
+                                 double dy, double dz, const int split[3], void *stream)
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
     return adjoint_step(0, lam_n, lam_np1, T_n, Ci, gCi, lam, dt, dx, dy, dz, split, stream);
 }
 
@@ -759,6 +797,9 @@ int diffusion_flux_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1
                                 const igg_field *Ci, const igg_field *gCi, double lam, double dt, double dx,
                                 double dy, double dz, const int split[3], void *stream)
 {
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    if (g.nranks > 1) return fail(IGG_ERR_STATE, "this entry point runs on a single-rank grid");
     return adjoint_step(1, lam_n, lam_np1, T_n, Ci, gCi, lam, dt, dx, dy, dz, split, stream);
 }
 

@@ -119,3 +119,49 @@ def test_step_ranks_equal_global_block(n, dims, periods, ol, dt_name):
                 a, b = b, a
             for r, c in enumerate(ranks):
                 assert np.array_equal(host(a[r]), _block(glob, c, n, ol)), (split, r, c)
+
+
+@pytest.mark.parametrize("n,dims,periods,ol", CASES)
+@pytest.mark.parametrize("dt_name", ["f64", "f32"])
+def test_adjoint_ranks_equal_global_block(n, dims, periods, ol, dt_name):
+    """Three adjoint steps on the ranks (split and unsplit) give the global
+    block's lam_n bit for bit, halos included, and its gCi on every block's
+    inner points."""
+    N = _global_n(n, ol, dims)
+    rng = np.random.default_rng(47)
+    lam0, Tn, Ci = (rng.uniform(0.3, 0.9, (N[2], N[1], N[0])) for _ in range(3))
+    for a in (lam0, Tn, Ci):
+        oracle.halo(a, ol, periods)
+    dx = 1.0 / (N[0] - 1)
+    dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
+    wdt = DT[dt_name]
+    steps = 3
+    with grid(N, periods, ol):
+        say("adjoint global block", N, dt_name)
+        lp, T, C = dev(lam0, wdt), dev(Tn, wdt), dev(Ci, wdt)
+        g = torch.zeros_like(lp)
+        for _ in range(steps):
+            ln = lp.clone()
+            igg.diffusion_step_adjoint(ln, lp, T, C, g, 1.0, dt, dx, dx, dx, split=None)
+            lp = ln
+        glob_l, glob_g = host(lp), host(g)
+    ranks = _ranks(dims)
+    for split in [None, (4, 3, 3)]:
+        if split is not None and any(w < o for w, o in zip(split, ol)):
+            continue
+        with grid(n, periods, ol, dims=dims):
+            say("adjoint ranks", n, dims, periods, ol, dt_name, split)
+            lps = [dev(_block(lam0, c, n, ol), wdt) for c in ranks]
+            Ts = [dev(_block(Tn, c, n, ol), wdt) for c in ranks]
+            Cs = [dev(_block(Ci, c, n, ol), wdt) for c in ranks]
+            gs = [torch.zeros_like(t) for t in lps]
+            for _ in range(steps):
+                lns = [t.clone() for t in lps]
+                igg.diffusion_step_adjoint_ranks(lns, lps, Ts, Cs, gs, 1.0, dt, dx, dx, dx, split=split)
+                lps = lns
+            for r, c in enumerate(ranks):
+                assert np.array_equal(host(lps[r]), _block(glob_l, c, n, ol)), (split, r)
+                # gCi is accumulated on each block's inner points (its halo
+                # stays as it was); those tile the global block's inner points
+                assert np.array_equal(host(gs[r])[1:-1, 1:-1, 1:-1],
+                                      _block(glob_g, c, n, ol)[1:-1, 1:-1, 1:-1]), (split, r)
