@@ -262,6 +262,16 @@ int diffusion_flux_step(const igg_field *T2, const igg_field *T, const igg_field
                         const igg_field *qx, const igg_field *qy, const igg_field *qz, double lam,
                         double dt, double dx, double dy, double dz, const int split[3], void *stream);
 
+/* diffusion_flux_step for every rank of the grid: each argument is an array
+ * of nranks fields (rank r's blocks; the face fields one point longer in
+ * their own dimension).  The x exchange of all four fields stores into the
+ * x neighbours' blocks and one igg_update_halo_ranks of {T2, qx, qy, qz}
+ * follows; the result equals the flux step on one block of the global grid
+ * bit for bit.  Errors: as diffusion_flux_step, naming the rank. */
+int diffusion_flux_step_ranks(const igg_field *T2, const igg_field *T, const igg_field *Ci,
+                              const igg_field *qx, const igg_field *qy, const igg_field *qz, double lam,
+                              double dt, double dx, double dy, double dz, const int split[3], void *stream);
+
 /* Adjoint of diffusion_flux_step.  With mu = Ci.*lam_np1 and the face
  * fluxes p = -lam*grad(mu) and q_n = -lam*grad(T_n) (the forward fluxes of
  * step n) formed per cell from its neighbours, as the forward pass forms q:
@@ -273,6 +283,13 @@ int diffusion_flux_step(const igg_field *T2, const igg_field *T, const igg_field
 int diffusion_flux_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1, const igg_field *T_n,
                                 const igg_field *Ci, const igg_field *gCi, double lam, double dt, double dx,
                                 double dy, double dz, const int split[3], void *stream);
+
+/* diffusion_flux_step_adjoint for every rank of the grid (arrays of nranks
+ * fields, as diffusion_step_adjoint_ranks).  Errors: as
+ * diffusion_flux_step_adjoint, naming the rank. */
+int diffusion_flux_step_adjoint_ranks(const igg_field *lam_n, const igg_field *lam_np1, const igg_field *T_n,
+                                      const igg_field *Ci, const igg_field *gCi, double lam, double dt, double dx,
+                                      double dy, double dz, const int split[3], void *stream);
 
 /* --------------------------------------------------------- reductions */
 

@@ -508,6 +508,108 @@ static int adjoint_step(int form, const igg_field *lam_n, const igg_field *lam_n
         [&](int r, const Box &b, hipStream_t st) { return launch_adjoint_inner(dt_, args[r], b, st); }, s);
 }
 
+static int check_face(const igg_field *q, const char *name, int dim)
+{
+    Grid &g = grid();
+    int rc;
+    if ((rc = check_field(q, name, false))) return rc;
+    for (int d = 0; d < 3; ++d)
+        if (q->size[d] != g.n[d] + (d == dim ? 1 : 0))
+            return fail(IGG_ERR_SIZE, std::string(name) + " must have n+1 points in its own dimension "
+                                                          "and n in the others");
+    return IGG_OK;
+}
+
+
+// The fused flux-form step for the grid's nranks ranks: each argument is an
+// array of one field per rank (a single field on a one-rank grid).
+static int flux_step_ranks(const igg_field *T2, const igg_field *T, const igg_field *Ci, const igg_field *qx,
+                           const igg_field *qy, const igg_field *qz, double lam, double dt, double dx, double dy,
+                           double dz, const int split[3], void *stream)
+{
+    Grid &g = grid();
+    int rc;
+    const int P = g.nranks;
+    if (!T2 || !T || !Ci || !qx || !qy || !qz) return fail(IGG_ERR_ARG, "null field");
+    const int ty = T[0].dtype;
+    for (int r = 0; r < P; ++r) {
+        const std::string sfx = P > 1 ? "[" + std::to_string(r) + "]" : "";
+        if ((rc = check_field(&T2[r], ("T2" + sfx).c_str(), true))) return rc;
+        if ((rc = check_field(&T[r], ("T" + sfx).c_str(), true))) return rc;
+        if ((rc = check_field(&Ci[r], ("Ci" + sfx).c_str(), true))) return rc;
+        if ((rc = check_face(&qx[r], ("qx" + sfx).c_str(), 0))) return rc;
+        if ((rc = check_face(&qy[r], ("qy" + sfx).c_str(), 1))) return rc;
+        if ((rc = check_face(&qz[r], ("qz" + sfx).c_str(), 2))) return rc;
+        for (const igg_field *f : {&T2[r], &T[r], &Ci[r], &qx[r], &qy[r], &qz[r]})
+            if (f->dtype != ty) return fail(IGG_ERR_DTYPE, "flux-form fields must share one dtype");
+    }
+    if (ty == IGG_F16) return fail(IGG_ERR_DTYPE, "the flux form runs in FP64 or FP32");
+    for (int r = 0; r < P; ++r) {
+        const igg_field *outs[4] = {&T2[r], &qx[r], &qy[r], &qz[r]};
+        for (int o = 0; o < 4; ++o)
+            for (int q = 0; q < P; ++q) {
+                if (overlaps_mem(*outs[o], T[q]) || overlaps_mem(*outs[o], Ci[q]))
+                    return fail(IGG_ERR_ALIAS, "an output shares memory with T or Ci");
+                const igg_field *others[4] = {&T2[q], &qx[q], &qy[q], &qz[q]};
+                for (int p = 0; p < 4; ++p)
+                    if ((q != r || p != o) && overlaps_mem(*outs[o], *others[p]))
+                        return fail(IGG_ERR_ALIAS, "outputs share memory");
+            }
+    }
+    if ((rc = check_spacings(lam, dt, dx, dy, dz))) return rc;
+    // the face fields overlap their neighbours by ol+1 planes in their own
+    // dimension, so each split width must cover that many planes
+    const int olf[3] = {g.ol[0] + 1, g.ol[1] + 1, g.ol[2] + 1};
+    if ((rc = check_split(split, olf))) return rc;
+    // per rank: the x exchange of all four fields is stored by the flux pass
+    // into the x neighbours' arrays; the halo update then moves y and z
+    std::vector<FluxArgs> args(P);
+    const int64_t esz = elem_bytes(ty);
+    for (int r = 0; r < P; ++r) {
+        FluxXH xh{};
+        xh.ol = g.ol[0];
+        if (g.fuse_x)
+            for (int side = 0; side < 2; ++side) {
+                const int q = rank_neighbor(r, 0, side);
+                if (q < 0) continue;
+                const igg_field *mine[4] = {&T2[r], &qx[r], &qy[r], &qz[r]};
+                const igg_field *theirs[4] = {&T2[q], &qx[q], &qy[q], &qz[q]};
+                for (int a = 0; a < 4; ++a) {
+                    const int64_t diff = (int64_t)((intptr_t)theirs[a]->data - (intptr_t)mine[a]->data);
+                    if (diff % esz) return fail(IGG_ERR_ARG, "flux-form blocks must be aligned to their element size");
+                    (side == 0 ? xh.d_lo : xh.d_hi)[a] = diff / esz;
+                }
+                (side == 0 ? xh.on_lo : xh.on_hi) = 1;
+            }
+        args[r] = FluxArgs{qx[r].data, qy[r].data, qz[r].data, T[r].data, T2[r].data, Ci[r].data, g.n[0], g.n[1],
+                           g.n[2], lam, dt, 1.0 / dx, 1.0 / dy, 1.0 / dz, ty, xh};
+    }
+    if ((rc = ensure_device())) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int halo_dims = g.fuse_x ? 6 : 7;
+    std::vector<igg_field> hf((size_t)4 * P);
+    for (int r = 0; r < P; ++r) {
+        hf[4 * r] = T2[r];
+        hf[4 * r + 1] = qx[r];
+        hf[4 * r + 2] = qy[r];
+        hf[4 * r + 3] = qz[r];
+    }
+    if (!split) {
+        Box all{1, g.n[0] - 1, 1, g.n[1] - 1, 1, g.n[2] - 1};
+        for (int r = 0; r < P; ++r) {
+            if ((rc = timing_mark(s, 0))) return rc;
+            if ((rc = launch_flux_inner(ty, args[r], all, s))) return rc;
+            if ((rc = timing_mark(s, 0))) return rc;
+            if (g.timing) { g.t_launches++; g.t_points += box_points(all); }
+        }
+        return launch_halo(hf.data(), 4, s, halo_dims);
+    }
+    return run_split(
+        split, hf.data(), 4, halo_dims,
+        [&](int r, const Split &b, hipStream_t st) { return launch_flux_boxes(ty, args[r], b.boundary, b.nb, st); },
+        [&](int r, const Box &b, hipStream_t st) { return launch_flux_inner(ty, args[r], b, st); }, s);
+}
+
 }  // namespace igg
 
 using namespace igg;
@@ -728,17 +830,6 @@ int diffusion_step_adjoint_ranks(const igg_field *lam_n, const igg_field *lam_np
     return adjoint_step(0, lam_n, lam_np1, T_n, Ci, gCi, lam, dt, dx, dy, dz, split, stream);
 }
 
-static int check_face(const igg_field *q, const char *name, int dim)
-{
-    Grid &g = grid();
-    int rc;
-    if ((rc = check_field(q, name, false))) return rc;
-    for (int d = 0; d < 3; ++d)
-        if (q->size[d] != g.n[d] + (d == dim ? 1 : 0))
-            return fail(IGG_ERR_SIZE, std::string(name) + " must have n+1 points in its own dimension "
-                                                          "and n in the others");
-    return IGG_OK;
-}
 
 int diffusion_flux_step(const igg_field *T2, const igg_field *T, const igg_field *Ci,
                         const igg_field *qx, const igg_field *qy, const igg_field *qz, double lam,
@@ -746,51 +837,17 @@ int diffusion_flux_step(const igg_field *T2, const igg_field *T, const igg_field
 {
     Grid &g = grid();
     if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
-    if (g.nranks > 1) return fail(IGG_ERR_STATE, "this entry point runs on a single-rank grid");
-    int rc;
-    if ((rc = check_field(T2, "T2", true))) return rc;
-    if ((rc = check_field(T, "T", true))) return rc;
-    if ((rc = check_field(Ci, "Ci", true))) return rc;
-    if ((rc = check_face(qx, "qx", 0))) return rc;
-    if ((rc = check_face(qy, "qy", 1))) return rc;
-    if ((rc = check_face(qz, "qz", 2))) return rc;
-    int ty = T->dtype;
-    for (const igg_field *f : {T2, Ci, qx, qy, qz})
-        if (f->dtype != ty) return fail(IGG_ERR_DTYPE, "flux-form fields must share one dtype");
-    if (ty == IGG_F16) return fail(IGG_ERR_DTYPE, "the flux form runs in FP64 or FP32");
-    const igg_field *outs[4] = {T2, qx, qy, qz};
-    for (int o = 0; o < 4; ++o) {
-        if (overlaps_mem(*outs[o], *T) || overlaps_mem(*outs[o], *Ci))
-            return fail(IGG_ERR_ALIAS, "an output shares memory with T or Ci");
-        for (int p = 0; p < o; ++p)
-            if (overlaps_mem(*outs[o], *outs[p])) return fail(IGG_ERR_ALIAS, "outputs share memory");
-    }
-    if ((rc = check_spacings(lam, dt, dx, dy, dz))) return rc;
-    // the face fields overlap their neighbours by ol+1 planes in their own
-    // dimension, so each split width must cover that many planes
-    const int olf[3] = {g.ol[0] + 1, g.ol[1] + 1, g.ol[2] + 1};
-    if ((rc = check_split(split, olf))) return rc;
-    if ((rc = ensure_device())) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    // the x exchange of all four fields is stored by the step kernels when x
-    // is periodic; the halo update then moves y and z
-    const int xon = (g.fuse_x && g.periods[0]) ? 1 : 0;
-    const int halo_dims = g.fuse_x ? 6 : 7;
-    FluxArgs a{qx->data, qy->data, qz->data, T->data, T2->data, Ci->data, g.n[0], g.n[1], g.n[2],
-               lam, dt, 1.0 / dx, 1.0 / dy, 1.0 / dz, ty, xon, g.ol[0]};
-    igg_field hf[4] = {*T2, *qx, *qy, *qz};
-    if (!split) {
-        Box all{1, g.n[0] - 1, 1, g.n[1] - 1, 1, g.n[2] - 1};
-        if ((rc = timing_mark(s, 0))) return rc;
-        if ((rc = launch_flux_inner(ty, a, all, s))) return rc;
-        if ((rc = timing_mark(s, 0))) return rc;
-        if (g.timing) { g.t_launches++; g.t_points += box_points(all); }
-        return launch_halo(hf, 4, s, halo_dims);
-    }
-    return run_split(
-        split, hf, 4, halo_dims,
-        [&](int, const Split &b, hipStream_t st) { return launch_flux_boxes(ty, a, b.boundary, b.nb, st); },
-        [&](int, const Box &b, hipStream_t st) { return launch_flux_inner(ty, a, b, st); }, s);
+    if (g.nranks > 1) return fail(IGG_ERR_STATE, "the grid holds several virtual ranks: use diffusion_flux_step_ranks");
+    return flux_step_ranks(T2, T, Ci, qx, qy, qz, lam, dt, dx, dy, dz, split, stream);
+}
+
+int diffusion_flux_step_ranks(const igg_field *T2, const igg_field *T, const igg_field *Ci,
+                              const igg_field *qx, const igg_field *qy, const igg_field *qz, double lam,
+                              double dt, double dx, double dy, double dz, const int split[3], void *stream)
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    return flux_step_ranks(T2, T, Ci, qx, qy, qz, lam, dt, dx, dy, dz, split, stream);
 }
 
 int diffusion_flux_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1, const igg_field *T_n,
@@ -799,7 +856,17 @@ int diffusion_flux_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1
 {
     Grid &g = grid();
     if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
-    if (g.nranks > 1) return fail(IGG_ERR_STATE, "this entry point runs on a single-rank grid");
+    if (g.nranks > 1)
+        return fail(IGG_ERR_STATE, "the grid holds several virtual ranks: use diffusion_flux_step_adjoint_ranks");
+    return adjoint_step(1, lam_n, lam_np1, T_n, Ci, gCi, lam, dt, dx, dy, dz, split, stream);
+}
+
+int diffusion_flux_step_adjoint_ranks(const igg_field *lam_n, const igg_field *lam_np1, const igg_field *T_n,
+                                      const igg_field *Ci, const igg_field *gCi, double lam, double dt, double dx,
+                                      double dy, double dz, const int split[3], void *stream)
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
     return adjoint_step(1, lam_n, lam_np1, T_n, Ci, gCi, lam, dt, dx, dy, dz, split, stream);
 }
 

@@ -23,17 +23,10 @@ static unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 // One pass per cell (i, j, k): its lower faces qx[i], qy[j], qz[k] (and the
 // upper face where the cell is the last of its row, column or plane), the
 // update T2 = T - dt*Ci*div(q) from the cell's six faces, and the x
-// exchange of all four fields when x is periodic on this single rank.  The
-// faces come from one expression (face_flux) and the divergence sums in a
-// fixed order (flux_div), so every value equals a face pass followed by a
-// cell pass.
-//
-// x exchange (this process its own x neighbour): T2, qy and qz (nx points
-// in x, overlap ol) copy column ol-1 to nx-1 and nx-ol to 0; qx (nx+1
-// faces, overlap ol+1) copies face ol to nx and face nx-ol to 0.
-struct FluxXH {
-    int on, ol;
-};
+// exchange of all four fields with the x neighbours (FluxXH).  The faces
+// come from one expression (face_flux) and the divergence sums in a fixed
+// order (flux_div), so every value equals a face pass followed by a cell
+// pass.
 
 // Stores of one cell that are not plain per-cell stores: the upper faces at
 // the ends and the x-exchange copies.  p: the cell's offset in a cell-sized
@@ -50,24 +43,27 @@ __device__ __forceinline__ void flux_extra_stores(C *T2, C *qx, C *qy, C *qz, in
     if (lastx) qx[px + 1] = qxu;
     if (lasty) qy[py + nx] = qyu;
     if (lastz) qz[p + sz] = qzu;
-    if (!xh.on) return;
-    // T2, qy, qz: column ol-1 -> nx-1, column nx-ol -> 0
+    // T2, qy, qz: column ol-1 -> lower neighbour's nx-1, column nx-ol ->
+    // upper neighbour's 0
     for (int side = 0; side < 2; ++side) {
+        if (!(side == 0 ? xh.on_lo : xh.on_hi)) continue;
         const int src = side == 0 ? xh.ol - 1 : nx - xh.ol;
         if (i != src) continue;
         const int64_t sh = side == 0 ? (int64_t)(nx - 1 - i) : -(int64_t)i;
-        T2[p + sh] = v2;
-        qy[py + sh] = qyl;
-        qz[p + sh] = qzl;
-        if (lasty) qy[py + nx + sh] = qyu;
-        if (lastz) qz[p + sz + sh] = qzu;
+        const int64_t *d = side == 0 ? xh.d_lo : xh.d_hi;
+        T2[p + sh + d[0]] = v2;
+        qy[py + sh + d[2]] = qyl;
+        qz[p + sh + d[3]] = qzl;
+        if (lasty) qy[py + nx + sh + d[2]] = qyu;
+        if (lastz) qz[p + sz + sh + d[3]] = qzu;
     }
-    // qx: face ol -> nx, face nx-ol -> 0 (faces i, and i+1 at the last cell)
+    // qx: face ol -> lower neighbour's nx, face nx-ol -> upper neighbour's 0
+    // (faces i, and i+1 at the last cell)
     for (int f = i; f <= (lastx ? i + 1 : i); ++f) {
         const C v = f == i ? qxl : qxu;
         const int64_t pf = px + (f - i);
-        if (f == xh.ol) qx[pf + (nx - f)] = v;
-        if (f == nx - xh.ol) qx[pf - f] = v;
+        if (xh.on_lo && f == xh.ol) qx[pf + (nx - f) + xh.d_lo[1]] = v;
+        if (xh.on_hi && f == nx - xh.ol) qx[pf - f + xh.d_hi[1]] = v;
     }
 }
 
@@ -274,7 +270,8 @@ k_flux_fused_zmarch(C *__restrict__ T2, C *__restrict__ qx, C *__restrict__ qy, 
                     qz[p + q] = fel<C, VEC>(oz, q);
                 }
                 qx[px + q] = oxl[q];
-                if (ii == nx - 2 || j == ny - 2 || k == z.g.nz - 2 || (z.xh.on && (ii <= z.xh.ol || ii >= nx - z.xh.ol)))
+                if (ii == nx - 2 || j == ny - 2 || k == z.g.nz - 2 ||
+                    ((z.xh.on_lo || z.xh.on_hi) && (ii <= z.xh.ol || ii >= nx - z.xh.ol)))
                     flux_extra_stores<C>(T2, qx, qy, qz, ii, j, k, p + q, px + q, py + q, z.g, z.xh,
                                          fel<C, VEC>(o2, q), oxl[q], oxu[q], fel<C, VEC>(oy, q), oyu[q],
                                          fel<C, VEC>(oz, q), ozu[q]);
@@ -305,9 +302,8 @@ static int run_fused_boxes(const FluxArgs &a, const Box *b, int nb, hipStream_t 
     const int64_t threads = bs.first[nb];
     if (threads == 0) return IGG_OK;
     FaceGeom g{a.nx, a.ny, a.nz};
-    FluxXH xh{a.xon, a.ol};
     hipLaunchKernelGGL(k_flux_fused_boxes<C>, dim3(blocks_for(threads)), dim3(256), 0, s, (C *)a.T2, (C *)a.qx,
-                       (C *)a.qy, (C *)a.qz, (const C *)a.T, (const C *)a.Ci, bs, g, xh, (C)a.lam, (C)a.dt,
+                       (C *)a.qy, (C *)a.qz, (const C *)a.T, (const C *)a.Ci, bs, g, a.xh, (C)a.lam, (C)a.dt,
                        (C)a.rdx, (C)a.rdy, (C)a.rdz);
     IGG_HIP(hipGetLastError());
     return IGG_OK;
@@ -320,7 +316,7 @@ static int run_fused_zmarch(const FluxArgs &a, const Box &b, hipStream_t s)
     FluxTile z{};
     z.b = b;
     z.g = FaceGeom{a.nx, a.ny, a.nz};
-    z.xh = FluxXH{a.xon, a.ol};
+    z.xh = a.xh;
     z.xa = (b.i0 / VEC) * VEC;
     z.ntx = (b.i1 - z.xa + TW - 1) / TW;
     z.nty = (b.j1 - b.j0 + TH - 1) / TH;

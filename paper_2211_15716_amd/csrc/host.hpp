@@ -162,6 +162,18 @@ struct AdjArgs {
 int launch_adjoint_boxes(int dtype, const AdjArgs &a, const Box *b, int nb, hipStream_t s);
 int launch_adjoint_inner(int dtype, const AdjArgs &a, const Box &b, hipStream_t s);
 
+// x exchange of the four flux-form fields fused into the flux pass: T2, qy
+// and qz (nx points in x, overlap ol) send column ol-1 to the lower x
+// neighbour's column nx-1 and column nx-ol to the upper neighbour's column
+// 0; qx (nx+1 faces, overlap ol+1) sends face ol to the lower neighbour's
+// face nx and face nx-ol to the upper neighbour's face 0.  d_lo[a] and
+// d_hi[a] are the neighbours' arrays' offsets from the own ones in elements,
+// a = T2, qx, qy, qz (0 when the process is its own neighbour).
+struct FluxXH {
+    int on_lo, on_hi, ol;
+    int64_t d_lo[4], d_hi[4];
+};
+
 struct FluxArgs {
     void *qx, *qy, *qz;
     const void *T;
@@ -170,7 +182,7 @@ struct FluxArgs {
     int nx, ny, nz;
     double lam, dt, rdx, rdy, rdz;
     int dtype;
-    int xon, ol;  // x exchange of T2, qx, qy, qz fused into the stores; the x overlap
+    FluxXH xh;  // x exchange of T2, qx, qy, qz fused into the stores
 };
 // The fused flux-form step (faces, update, x exchange) over boxes of cells:
 // one thread per cell, or z-march tiles for a large region.

@@ -35,7 +35,7 @@ EXPORTS = ["igg_init_global_grid", "igg_global_size", "igg_topology", "igg_updat
            "diffusion_flux_step", "diffusion_flux_step_adjoint", "igg_reduce", "igg_plan_split",
            "igg_timing_enable", "igg_timing_read", "igg_last_error", "igg_version",
            "igg_nranks", "igg_rank_coords", "igg_neighbors", "igg_update_halo_ranks", "diffusion_step_ranks",
-           "diffusion_step_adjoint_ranks"]
+           "diffusion_step_adjoint_ranks", "diffusion_flux_step_ranks", "diffusion_flux_step_adjoint_ranks"]
 
 
 class IggError(RuntimeError):
@@ -85,6 +85,8 @@ def load():
     lib.diffusion_dt.argtypes = [_PF, d, d, d, d, ctypes.POINTER(d), vp]
     lib.diffusion_step_adjoint.argtypes = [_PF] * 5 + [d] * 5 + [_PI, vp]
     lib.diffusion_step_adjoint_ranks.argtypes = [_PF] * 5 + [d] * 5 + [_PI, vp]
+    lib.diffusion_flux_step_ranks.argtypes = [_PF] * 6 + [d] * 5 + [_PI, vp]
+    lib.diffusion_flux_step_adjoint_ranks.argtypes = [_PF] * 5 + [d] * 5 + [_PI, vp]
     lib.diffusion_flux_step.argtypes = [_PF] * 6 + [d] * 5 + [_PI, vp]
     lib.diffusion_flux_step_adjoint.argtypes = [_PF] * 5 + [d] * 5 + [_PI, vp]
     lib.igg_reduce.argtypes = [ctypes.c_int, _PF, _PF, ctypes.POINTER(d), vp]
@@ -240,6 +242,21 @@ def diffusion_step_adjoint_ranks(lam_ns, lam_np1s, T_ns, Cis, gCis, lam, dt, dx,
     arrs = [(Field * len(ts))(*[field(t) for t in ts]) for ts in (lam_ns, lam_np1s, T_ns, Cis, gCis)]
     _check(load().diffusion_step_adjoint_ranks(*arrs, float(lam), float(dt), float(dx), float(dy), float(dz),
                                                _int3(split), _stream(stream)))
+
+
+def diffusion_flux_step_ranks(T2s, Ts, Cis, qxs, qys, qzs, lam, dt, dx, dy, dz, split=None, stream=None):
+    """diffusion_flux_step on every rank's blocks (lists with one tensor per rank)."""
+    arrs = [(Field * len(ts))(*[field(t) for t in ts]) for ts in (T2s, Ts, Cis, qxs, qys, qzs)]
+    _check(load().diffusion_flux_step_ranks(*arrs, float(lam), float(dt), float(dx), float(dy), float(dz),
+                                            _int3(split), _stream(stream)))
+
+
+def diffusion_flux_step_adjoint_ranks(lam_ns, lam_np1s, T_ns, Cis, gCis, lam, dt, dx, dy, dz, split=None,
+                                      stream=None):
+    """diffusion_flux_step_adjoint on every rank's block."""
+    arrs = [(Field * len(ts))(*[field(t) for t in ts]) for ts in (lam_ns, lam_np1s, T_ns, Cis, gCis)]
+    _check(load().diffusion_flux_step_adjoint_ranks(*arrs, float(lam), float(dt), float(dx), float(dy),
+                                                    float(dz), _int3(split), _stream(stream)))
 
 
 def diffusion_dt(Ci, lam, dx, dy, dz, stream=None):

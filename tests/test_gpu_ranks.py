@@ -165,3 +165,63 @@ def test_adjoint_ranks_equal_global_block(n, dims, periods, ol, dt_name):
                 # stays as it was); those tile the global block's inner points
                 assert np.array_equal(host(gs[r])[1:-1, 1:-1, 1:-1],
                                       _block(glob_g, c, n, ol)[1:-1, 1:-1, 1:-1]), (split, r)
+
+
+@pytest.mark.parametrize("n,dims,periods,ol", CASES)
+def test_flux_ranks_equal_global_block(n, dims, periods, ol):
+    """The fused flux-form step on the ranks (split and unsplit): T and the
+    three face fields equal the global block's bit for bit, halos included;
+    then three flux-form adjoint steps give its lam_n (halos included) and
+    gCi (inner points)."""
+    N = _global_n(n, ol, dims)
+    T0, Ci = _global_problem(N, periods, ol, 53)
+    dx = 1.0 / (N[0] - 1)
+    dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
+    nt = 4
+    fshape = [(N[2], N[1], N[0] + 1), (N[2], N[1] + 1, N[0]), (N[2] + 1, N[1], N[0])]
+    extra = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    with grid(N, periods, ol):
+        say("flux global block", N)
+        T, C = dev(T0), dev(Ci)
+        W = T.clone()
+        q = [torch.zeros(s, dtype=torch.float64, device="cuda") for s in fshape]
+        for _ in range(nt):
+            igg.diffusion_flux_step(W, T, C, *q, 1.0, dt, dx, dx, dx)
+            T, W = W, T
+        glob_T, glob_q = host(T), [host(x) for x in q]
+        lp, g = T.clone(), torch.zeros_like(T)
+        for _ in range(3):
+            ln = lp.clone()
+            igg.diffusion_flux_step_adjoint(ln, lp, T, C, g, 1.0, dt, dx, dx, dx)
+            lp = ln
+        glob_l, glob_g = host(lp), host(g)
+    ranks = _ranks(dims)
+    for split in [None, (4, 3, 3)]:
+        if split is not None and any(w < o + 1 for w, o in zip(split, ol)):
+            continue
+        with grid(n, periods, ol, dims=dims):
+            say("flux ranks", n, dims, periods, ol, split)
+            Ts = [dev(_block(T0, c, n, ol)) for c in ranks]
+            Cs = [dev(_block(Ci, c, n, ol)) for c in ranks]
+            Ws = [t.clone() for t in Ts]
+            qs = [[torch.zeros(tuple(m + e for m, e in zip((n[2], n[1], n[0]), reversed(ex))),
+                               dtype=torch.float64, device="cuda") for ex in extra] for _ in ranks]
+            a, b = Ts, Ws
+            for _ in range(nt):
+                igg.diffusion_flux_step_ranks(b, a, Cs, [x[0] for x in qs], [x[1] for x in qs], [x[2] for x in qs],
+                                              1.0, dt, dx, dx, dx, split=split)
+                a, b = b, a
+            for r, c in enumerate(ranks):
+                assert np.array_equal(host(a[r]), _block(glob_T, c, n, ol)), (split, r)
+                for d in range(3):
+                    assert np.array_equal(host(qs[r][d]), _block(glob_q[d], c, n, ol, extra[d])), (split, r, d)
+            lps = [t.clone() for t in a]
+            gs = [torch.zeros_like(t) for t in a]
+            for _ in range(3):
+                lns = [t.clone() for t in lps]
+                igg.diffusion_flux_step_adjoint_ranks(lns, lps, a, Cs, gs, 1.0, dt, dx, dx, dx, split=split)
+                lps = lns
+            for r, c in enumerate(ranks):
+                assert np.array_equal(host(lps[r]), _block(glob_l, c, n, ol)), (split, r)
+                assert np.array_equal(host(gs[r])[1:-1, 1:-1, 1:-1],
+                                      _block(glob_g, c, n, ol)[1:-1, 1:-1, 1:-1]), (split, r)
