@@ -1,0 +1,80 @@
+"""Randomised parity sweep and extreme shapes: grid sizes from the smallest
+allowed (n = ol + 1) up, random periods, overlaps 2-4, split widths from the
+overlap up, every dtype; and long thin grids whose index products are large."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2211_15716_amd import diffusion, igg, synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+from gpu_common import dev, grid, host, say  # noqa: E402
+
+DT = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16}
+
+
+def _cases(count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        ol = tuple(int(v) for v in rng.integers(2, 5, size=3))
+        n = tuple(int(rng.integers(o + 1, o + 1 + int(rng.choice([2, 9, 40, 90])))) for o in ol)
+        periods = tuple(int(v) for v in rng.integers(0, 2, size=3))
+        split = None if rng.random() < 0.3 else tuple(int(rng.integers(o, o + 20)) for o in ol)
+        out.append((n, ol, periods, split))
+    return out
+
+
+@pytest.mark.parametrize("case", _cases(24, 2024))
+@pytest.mark.parametrize("zmin", [0, None])
+def test_random_grids_match_oracle(case, zmin):
+    """FP64 against the oracle (all points, halos included); FP32 and FP16
+    (stochastic rounding) split against unsplit bit for bit."""
+    n, ol, periods, split = case
+    nx, ny, nz = n
+    T0, Ci = synth.noisy_state_uniform_ci(nx, ny, nz, seed=sum(n), noise=1e-2)
+    oracle.halo(T0, ol, periods)
+    oracle.halo(Ci, ol, periods)
+    d = tuple(1.0 / (m - 1) for m in n)
+    dt = oracle.time_step(*d, 1.0, oracle.max_all(Ci))
+    nt = 3
+    ref = oracle.run(T0, Ci, nt, 1.0, dt, *d, ol=ol, periods=periods)
+    with grid(n, periods, ol, zmarch_min=zmin):
+        say("random grid", n, ol, periods, split, zmin)
+        got = host(diffusion.forward(dev(T0), dev(Ci), nt, 1.0, dt, *d, split=split))
+        assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+        for name in ("f32", "f16"):
+            seed = 3 if name == "f16" else None
+            a = host(diffusion.forward(dev(T0, DT[name]), dev(Ci, DT[name]), nt, 1.0, dt, *d, split=split,
+                                       sr_seed=seed))
+            b = host(diffusion.forward(dev(T0, DT[name]), dev(Ci, DT[name]), nt, 1.0, dt, *d, split=None,
+                                       sr_seed=seed))
+            assert np.array_equal(a, b), name
+
+
+@pytest.mark.parametrize("n,split", [((4096, 4096, 6), (16, 2, 2)), ((6, 6, 1 << 22), None)])
+def test_extreme_aspect_ratios(n, split):
+    """Grids of 10^8 points in a long thin shape (a 16.8 M-point plane, a
+    4 M-plane column): sampled points against the oracle's light cone after
+    3 steps, and the periodic halo of the result."""
+    nx, ny, nz = n
+    rng = np.random.default_rng(9)
+    T0 = 1.7 + 1e-2 * rng.standard_normal((nz, ny, nx))
+    Ci = rng.uniform(0.25, 0.75, (nz, ny, nx))
+    oracle.halo(T0)
+    oracle.halo(Ci)
+    d = (1.0 / (nx - 1), 1.0 / (ny - 1), 1.0 / (nz - 1))
+    dt = oracle.time_step(*d, 1.0, oracle.max_all(Ci))
+    nt = 3
+    pts = [(1, 1, 1), (nx - 2, ny - 2, nz - 2), (nx // 2, ny // 3, nz // 2), (nx - 2, 1, nz - 2),
+           (1, ny - 2, nz // 3)]
+    with grid(n, zmarch_min=None):
+        say("extreme", n, split)
+        out = diffusion.forward(dev(T0), dev(Ci), nt, 1.0, dt, *d, split=split)
+        got = np.array([out[k, j, i].item() for (i, j, k) in pts])
+        assert torch.equal(out[:, :, 0], out[:, :, -2]) and torch.equal(out[:, :, -1], out[:, :, 1])
+        assert torch.equal(out[0], out[-2]) and torch.equal(out[-1], out[1])
+        del out
+    ref = oracle.run_points(T0, Ci, nt, 1.0, dt, *d, pts)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
