@@ -210,6 +210,27 @@ int diffusion_step_ranks(const igg_field *T2, const igg_field *T, const igg_fiel
                          double dt, double dx, double dy, double dz, const int split[3],
                          const igg_rounding *rnd, void *stream);
 
+/* nt steps of Fig. 1's time loop on the buffers T and T2, which swap every
+ * step (step it reads buf[it % 2] and writes the other, buf = {T, T2}), with
+ * the same arguments as diffusion_step; *final_buf is set to the index of
+ * the buffer holding T_nt (0: T, 1: T2).  T2 must hold T's halo planes in
+ * non-periodic dimensions (Fig. 1 starts it as a copy of T).  rnd: the
+ * stochastic-rounding counter advances by one per step.
+ *   use_graph  0: every step is launched as diffusion_step would.  1: up to
+ *          8 pairs of steps T -> T2 -> T are captured once into a HIP graph
+ *          on a library stream and replayed on `stream`; the steps left over
+ *          run directly.  The graph is kept for later calls with identical
+ *          arguments (and pair count) and rebuilt when any differs.  For
+ *          grids small enough that launch latency dominates.  Stochastic
+ *          rounding needs a new counter every step, so it refuses
+ *          use_graph = 1.
+ * Results are bit-identical for both values of use_graph.
+ * Errors: as diffusion_step; IGG_ERR_ARG for nt < 0, a null final_buf, or
+ * use_graph with stochastic rounding. */
+int diffusion_run(const igg_field *T, const igg_field *T2, const igg_field *Ci, double lam, double dt,
+                  double dx, double dy, double dz, const int split[3], const igg_rounding *rnd, int nt,
+                  int use_graph, int *final_buf, void *stream);
+
 /* Stable time step of Fig. 1: dt = min(dx^2,dy^2,dz^2)/lam/maximum(Ci)/6.1,
  * the maximum taken in FP64 over every point of Ci on the GPU.
  * Synchronises `stream`.  Errors: as igg_reduce, IGG_ERR_ARG for lam <= 0. */

@@ -195,6 +195,11 @@ static int release_device()
     chk(hipEventDestroy(g.ev_join), "hipEventDestroy");
     for (hipEvent_t e : g.tev) chk(hipEventDestroy(e), "hipEventDestroy(timing)");
     chk(hipStreamDestroy(g.side), "hipStreamDestroy(side)");
+    if (g.run_exec) chk(hipGraphExecDestroy(g.run_exec), "hipGraphExecDestroy");
+    if (g.cap) chk(hipStreamDestroy(g.cap), "hipStreamDestroy(cap)");
+    g.run_exec = nullptr;
+    g.cap = nullptr;
+    g.run_key.clear();
     g.tev.clear();
     g.dev_ready = false;
     return rc;
@@ -789,6 +794,95 @@ int diffusion_step_ranks(const igg_field *T2, const igg_field *T, const igg_fiel
     if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
     if (!T2 || !T || !Ci) return fail(IGG_ERR_ARG, "null field array");
     return step_ranks(T2, T, Ci, lam, dt, dx, dy, dz, split, rnd, stream);
+}
+
+int diffusion_run(const igg_field *T, const igg_field *T2, const igg_field *Ci, double lam, double dt,
+                  double dx, double dy, double dz, const int split[3], const igg_rounding *rnd, int nt,
+                  int use_graph, int *final_buf, void *stream)
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    if (g.nranks > 1) return fail(IGG_ERR_STATE, "the grid holds several virtual ranks: use diffusion_step_ranks");
+    if (!T || !T2 || !Ci || !final_buf) return fail(IGG_ERR_ARG, "null argument");
+    if (nt < 0) return fail(IGG_ERR_ARG, "nt must be >= 0");
+    if (use_graph && rnd && rnd->mode == IGG_ROUND_STOCHASTIC)
+        return fail(IGG_ERR_ARG, "graph replays would repeat the stochastic-rounding counter: use_graph = 0");
+    hipStream_t s = (hipStream_t)stream;
+    int rc;
+    *final_buf = 0;
+    const igg_field *buf[2] = {T, T2};
+    auto eager = [&](int it) {
+        igg_rounding r{};
+        const igg_rounding *rp = nullptr;
+        if (rnd) {
+            r = *rnd;
+            r.counter += (uint64_t)it;
+            rp = &r;
+        }
+        const int src = it & 1;
+        return step_ranks(buf[1 - src], buf[src], Ci, lam, dt, dx, dy, dz, split, rp, stream);
+    };
+    if (!use_graph || nt < 2) {
+        for (int it = 0; it < nt; ++it)
+            if ((rc = eager(it))) return rc;
+        *final_buf = nt & 1;
+        return IGG_OK;
+    }
+    // the graph holds `pairs` pairs of steps T -> T2 -> T with these exact
+    // arguments (up to 8: one graph launch then covers 16 steps)
+    const int pairs = std::min(8, nt / 2);
+    std::vector<unsigned char> key;
+    auto put = [&](const void *p, size_t n) {
+        const unsigned char *c = (const unsigned char *)p;
+        key.insert(key.end(), c, c + n);
+    };
+    for (const igg_field *f : {T, T2, Ci}) put(f, sizeof(igg_field));
+    for (double v : {lam, dt, dx, dy, dz}) put(&v, sizeof v);
+    const int nosplit[3] = {-1, -1, -1};
+    put(split ? split : nosplit, 3 * sizeof(int));
+    const int mode = rnd ? rnd->mode : -1;
+    put(&mode, sizeof mode);
+    put(&pairs, sizeof pairs);
+    if (!g.run_exec || key != g.run_key) {
+        // a new argument set is captured: both steps run their argument
+        // checks while being recorded, and a failed check ends the capture
+        // without keeping anything
+        if ((rc = ensure_device())) return rc;
+        if (!g.cap) IGG_HIP(hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking));
+        if (g.run_exec) {
+            IGG_HIP(hipGraphExecDestroy(g.run_exec));
+            g.run_exec = nullptr;
+            g.run_key.clear();
+        }
+        const bool timing = g.timing;
+        g.timing = false;
+        IGG_HIP(hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal));
+        int rc2 = IGG_OK;
+        for (int p = 0; p < pairs && !rc2; ++p) {
+            rc2 = step_ranks(T2, T, Ci, lam, dt, dx, dy, dz, split, rnd, g.cap);
+            if (!rc2) rc2 = step_ranks(T, T2, Ci, lam, dt, dx, dy, dz, split, rnd, g.cap);
+        }
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(g.cap, &graph);
+        g.timing = timing;
+        if (rc2) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc2;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        g.run_exec = exec;
+        g.run_key = key;
+    }
+    const int replays = nt / (2 * pairs);
+    for (int p = 0; p < replays; ++p) IGG_HIP(hipGraphLaunch(g.run_exec, s));
+    for (int it = replays * 2 * pairs; it < nt; ++it)
+        if ((rc = eager(it))) return rc;
+    *final_buf = nt & 1;
+    return IGG_OK;
 }
 
 int diffusion_dt(const igg_field *Ci, double lam, double dx, double dy, double dz, double *dt,

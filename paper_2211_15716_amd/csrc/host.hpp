@@ -74,6 +74,12 @@ struct Grid {
     int fuse_x = 1;    // x exchange fused into the step kernels' stores
     int64_t zmarch_min = kZmarchMinPoints;  // smallest region for the z-march kernels
 
+    // diffusion_run's graph: two steps T -> T2 -> T captured on the capture
+    // stream, kept while every argument the kernels take stays the same
+    hipStream_t cap = nullptr;
+    hipGraphExec_t run_exec = nullptr;
+    std::vector<unsigned char> run_key;
+
     bool timing = false;
     std::vector<hipEvent_t> tev;  // start/stop pairs of timed launches
     std::vector<int> tev_kind;    // 0: inner-region kernel, 1: boundary kernels

@@ -35,7 +35,8 @@ EXPORTS = ["igg_init_global_grid", "igg_global_size", "igg_topology", "igg_updat
            "diffusion_flux_step", "diffusion_flux_step_adjoint", "igg_reduce", "igg_plan_split",
            "igg_timing_enable", "igg_timing_read", "igg_last_error", "igg_version",
            "igg_nranks", "igg_rank_coords", "igg_neighbors", "igg_update_halo_ranks", "diffusion_step_ranks",
-           "diffusion_step_adjoint_ranks", "diffusion_flux_step_ranks", "diffusion_flux_step_adjoint_ranks"]
+           "diffusion_step_adjoint_ranks", "diffusion_flux_step_ranks", "diffusion_flux_step_adjoint_ranks",
+           "diffusion_run"]
 
 
 class IggError(RuntimeError):
@@ -82,6 +83,8 @@ def load():
     lib.igg_finalize_global_grid.argtypes = []
     lib.diffusion_step.argtypes = [_PF] * 3 + [d] * 5 + [_PI, ctypes.POINTER(Rounding), vp]
     lib.diffusion_step_ranks.argtypes = [_PF] * 3 + [d] * 5 + [_PI, ctypes.POINTER(Rounding), vp]
+    lib.diffusion_run.argtypes = [_PF] * 3 + [d] * 5 + [_PI, ctypes.POINTER(Rounding), ctypes.c_int, ctypes.c_int,
+                                                        _PI, vp]
     lib.diffusion_dt.argtypes = [_PF, d, d, d, d, ctypes.POINTER(d), vp]
     lib.diffusion_step_adjoint.argtypes = [_PF] * 5 + [d] * 5 + [_PI, vp]
     lib.diffusion_step_adjoint_ranks.argtypes = [_PF] * 5 + [d] * 5 + [_PI, vp]
@@ -257,6 +260,19 @@ def diffusion_flux_step_adjoint_ranks(lam_ns, lam_np1s, T_ns, Cis, gCis, lam, dt
     arrs = [(Field * len(ts))(*[field(t) for t in ts]) for ts in (lam_ns, lam_np1s, T_ns, Cis, gCis)]
     _check(load().diffusion_flux_step_adjoint_ranks(*arrs, float(lam), float(dt), float(dx), float(dy),
                                                     float(dz), _int3(split), _stream(stream)))
+
+
+def diffusion_run(T, T2, Ci, lam, dt, dx, dy, dz, nt, split=(16, 2, 2), rnd=None, graph=True, stream=None):
+    """nt steps of the Fig. 1 time loop on the buffers T and T2 (swapped each
+    step); with graph=True the library replays a captured HIP graph of two
+    steps.  Returns the tensor holding the final state (T or T2)."""
+    fb = ctypes.c_int(0)
+    r = ctypes.byref(rnd) if rnd is not None else None
+    f, f2, fc = field(T), field(T2), field(Ci)
+    _check(load().diffusion_run(ctypes.byref(f), ctypes.byref(f2), ctypes.byref(fc), float(lam), float(dt), float(dx),
+                                float(dy), float(dz), _int3(split), r, int(nt), 1 if graph else 0, ctypes.byref(fb),
+                                _stream(stream)))
+    return T2 if fb.value else T
 
 
 def diffusion_dt(Ci, lam, dx, dy, dz, stream=None):

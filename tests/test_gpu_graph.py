@@ -42,3 +42,46 @@ def test_graph_replay_matches_eager(n, split, sched, monkeypatch):
             assert junk == 1000.0
         got = host(T)
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("n,split,dt_name", [((32, 32, 32), (16, 2, 2), "f64"), ((66, 40, 36), (16, 2, 2), "f32"),
+                                             ((48, 40, 36), None, "f64"), ((160, 140, 120), (16, 2, 2), "f64"),
+                                             ((40, 34, 30), (16, 2, 2), "f16")])
+def test_native_graph_run_matches_eager(n, split, dt_name):
+    """diffusion_run with the library's captured graph equals eager steps bit
+    for bit, for odd and even step counts, on repeated calls (the kept graph),
+    after the arguments change (a new capture), with eager torch work between
+    calls; FP16 with round-to-nearest stores."""
+    say("native graph", n, split, dt_name)
+    dt_map = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16}
+    T0, Ci = synth.noisy_state_uniform_ci(*n, seed=73, noise=1e-2)
+    oracle.halo(T0)
+    oracle.halo(Ci)
+    dx = 1 / (n[0] - 1)
+    dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
+    wdt = dt_map[dt_name]
+    with grid(n, zmarch_min=None):
+        C = dev(Ci, wdt)
+        for nt in (1, 4, 7, 6, 37, 16):
+            ref = host(diffusion.forward(dev(T0, wdt), C, nt, 1.0, dt, dx, dx, dx, split=split))
+            for rep in range(2):
+                T = dev(T0, wdt)
+                T2 = T.clone()
+                out = igg.diffusion_run(T, T2, C, 1.0, dt, dx, dx, dx, nt, split=split, graph=True)
+                assert torch.ones(100, device="cuda").sum().item() == 100.0
+                assert np.array_equal(host(out), ref), (nt, rep)
+        # a different time step: the kept graph must be rebuilt
+        ref = host(diffusion.forward(dev(T0, wdt), C, 4, 1.0, 0.5 * dt, dx, dx, dx, split=split))
+        T = dev(T0, wdt)
+        out = igg.diffusion_run(T, T.clone(), C, 1.0, 0.5 * dt, dx, dx, dx, 4, split=split, graph=True)
+        assert np.array_equal(host(out), ref)
+        if dt_name == "f16":
+            with pytest.raises(igg.IggError):
+                igg.diffusion_run(T, T.clone(), C, 1.0, dt, dx, dx, dx, 4, split=split,
+                                  rnd=igg.rounding("stochastic", 1, 0), graph=True)
+            # without the graph, stochastic rounding advances the counter per step
+            sr = host(diffusion.forward(dev(T0, wdt), C, 5, 1.0, dt, dx, dx, dx, split=split, sr_seed=9))
+            T = dev(T0, wdt)
+            out = igg.diffusion_run(T, T.clone(), C, 1.0, dt, dx, dx, dx, 5, split=split,
+                                    rnd=igg.rounding("stochastic", 9, 0), graph=False)
+            assert np.array_equal(host(out), sr)
