@@ -243,6 +243,9 @@ int diffusion_dt(const igg_field *Ci, double lam, double dx, double dy, double d
  *   lam_n = lam_np1 + a*L(Ci.*lam_np1)     (inner points), then halo(lam_n)
  *   gCi  += a*lam_np1.*(L T_n)             (inner points; halo untouched)
  * T_n is the state the forward step read (valid halo); Ci needs a valid halo.
+ * lam_np1 lives on the unique points: its halo is their periodic image in
+ * periodic dimensions and zero in non-periodic ones (lam_n's halo planes in
+ * non-periodic dimensions are not written, so start lam_n zeroed there).
  * FP64 or FP32 (IGG_ERR_DTYPE for FP16).  `split` as in diffusion_step.
  * Errors: as diffusion_step; IGG_ERR_ALIAS if lam_n or gCi overlaps an input
  * or each other. */

@@ -103,16 +103,52 @@ class FluxProblem:
                                         split=self.split, stream=stream)
 
 
+class RankProblem(Problem):
+    """The Laplacian time loop on a grid of several virtual ranks: states,
+    Ci and gradients are lists with one block per rank, and the steps go
+    through diffusion_step_ranks / diffusion_step_adjoint_ranks."""
+
+    def step(self, out, T, Ci, stream=None):
+        igg.diffusion_step_ranks(out, T, Ci, self.lam, self.dt, self.dx, self.dy, self.dz, split=self.split,
+                                 stream=stream)
+
+    def adjoint(self, lam_n, lam_np1, Tn, Ci, gCi, stream=None):
+        igg.diffusion_step_adjoint_ranks(lam_n, lam_np1, Tn, Ci, gCi, self.lam, self.dt, self.dx, self.dy, self.dz,
+                                         split=self.split, stream=stream)
+
+
+# states are tensors, or lists of per-rank blocks on a grid of virtual ranks
+def _map(f, x):
+    return [f(t) for t in x] if isinstance(x, (list, tuple)) else f(x)
+
+
+def _clone(x):
+    return _map(torch.clone, x)
+
+
+def _zeros_like(x):
+    return _map(torch.zeros_like, x)
+
+
+def _copy_(dst, src):
+    if isinstance(dst, (list, tuple)):
+        for d, s_ in zip(dst, src):
+            d.copy_(s_)
+    else:
+        dst.copy_(src)
+
+
 class Sweep:
     """Runs a checkpointing schedule (paper_2211_15716_amd.checkpoint) on the
-    GPU.  Snapshots are device tensors; the current state is either a
-    snapshot (read only) or one of two work buffers, so advancing never
-    overwrites a snapshot.  Counts forward and adjoint steps."""
+    GPU.  Snapshots are device tensors (lists of per-rank blocks with a
+    RankProblem); the current state is either a snapshot (read only) or one
+    of two work buffers, so advancing never overwrites a snapshot.  Counts
+    forward and adjoint steps."""
 
     def __init__(self, prob, Ci, T0, ops):
         self.p, self.Ci, self.ops = prob, Ci, ops
         self.store = {0: T0}
-        self.work = [T0.clone(), T0.clone()]  # halo planes of non-periodic dimensions
+        self.work = [_clone(T0), _clone(T0)]  # halo planes of non-periodic dimensions
         self.cur, self.cur_n = T0, 0
         self.advances = 0
         self.adjoints = 0
@@ -136,7 +172,7 @@ class Sweep:
             self._advance(op[1], op[2])
         elif kind == "store":
             assert self.cur_n == op[1]
-            self.store[op[1]] = self.cur.clone()
+            self.store[op[1]] = _clone(self.cur)
             self.peak = max(self.peak, len(self.store))
         elif kind == "free":
             if op[1] != 0:
@@ -148,20 +184,20 @@ class Sweep:
         """The forward sweep; returns T_nt (a new tensor)."""
         for op in self.fwd:
             self._do(op)
-        out = torch.empty_like(self.cur)
+        out = _clone(self.cur)  # a copy keeps the non-periodic halo planes
         if nt > 0:
             self.p.step(out, self.cur, self.Ci)
             self.advances += 1
-        else:
-            out.copy_(self.cur)
         return out
 
     def reverse(self, lam_nt):
         """The reverse sweep from lam_nt = dLoss/dT_nt (valid halo); returns
         (dLoss/dT_0, dLoss/dCi) with the Ci gradient on the inner points."""
         lp = lam_nt
-        ln = torch.empty_like(lp)
-        gCi = torch.zeros_like(lp)
+        # lambda lives on the unique points: its halo planes in non-periodic
+        # dimensions stay zero (the adjoint steps never write them)
+        ln = _zeros_like(lp)
+        gCi = _zeros_like(lp)
         for op in self.rev:
             if op[0] == "adjoint":
                 assert self.cur_n == op[1], (op, self.cur_n)
@@ -235,6 +271,24 @@ def loss_and_grad(T0, Ci, T_obs, prob, nt, schedule=("store_all",)):
     igg.update_halo(lam_nt)
     gT0, gCi = sweep.reverse(lam_nt)
     return L, _inner_only(gT0), _inner_only(gCi), sweep
+
+
+def loss_and_grad_ranks(T0s, Cis, T_obs_s, prob, nt, schedule=("store_all",)):
+    """loss_and_grad on a grid of virtual ranks (lists of per-rank blocks,
+    prob a RankProblem).  The blocks' inner points tile the global grid's
+    unique points when the overlaps are 2, so the loss is the sum of the
+    blocks' FP64 sums; other overlaps are refused."""
+    from . import checkpoint
+    if tuple(igg.topology()["overlaps"]) != (2, 2, 2):
+        raise ValueError("loss_and_grad_ranks needs overlaps (2, 2, 2)")
+    ops = checkpoint.make(schedule[0], nt, schedule[1] if len(schedule) > 1 else None)
+    sweep = Sweep(prob, Cis, T0s, ops)
+    Tnt = sweep.forward(nt)
+    L = sum(igg.reduce(igg.RED_HALF_SQDIFF, a, b) for a, b in zip(Tnt, T_obs_s))
+    lam_nt = [_inner_only(a - b) for a, b in zip(Tnt, T_obs_s)]
+    igg.update_halo_ranks(*[(t,) for t in lam_nt])
+    gT0, gCi = sweep.reverse(lam_nt)
+    return L, [_inner_only(t) for t in gT0], [_inner_only(t) for t in gCi], sweep
 
 
 # --------------------------------------------------------------------------- graph capture

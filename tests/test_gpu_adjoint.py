@@ -115,6 +115,31 @@ def test_adjoint_schedules_and_x_exchange_forms_equal(monkeypatch):
     assert np.max(np.abs(inner(gC) - inner(gC_ref))) <= 1e-12 * np.max(np.abs(inner(gC_ref)))
 
 
+@pytest.mark.parametrize("periods", [(1, 0, 1), (0, 0, 0), (0, 1, 1)])
+def test_checkpointed_gradient_non_periodic_matches_oracle(periods):
+    """Non-periodic dimensions: the boundary planes are fixed inputs, the
+    adjoint's halo there is zero; every schedule gives the oracle's loss and
+    gradients."""
+    say("non-periodic gradient", periods)
+    n = (40, 34, 30)
+    nt = 9
+    T0, Ci, Tobs = synth.uniform_fields(*n, seed=63, lo=0.3, hi=0.9, n=3)
+    for a in (T0, Ci, Tobs):
+        oracle.halo(a, (2, 2, 2), periods)
+    dx = 1 / 39
+    dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
+    L_ref, gT_ref, gC_ref = oracle.gradient(T0, Ci, Tobs, nt, 1.0, dt, dx, dx, dx, periods=periods)
+    with grid(n, periods):
+        for split in (None, (16, 2, 2)):
+            prob = diffusion.Problem(1.0, dt, dx, dx, dx, split=split)
+            for sched in [("store_all",), ("periodic", 4), ("binomial", 2)]:
+                L, gT, gC, _ = diffusion.loss_and_grad(dev(T0), dev(Ci), dev(Tobs), prob, nt, sched)
+                gT, gC = host(gT), host(gC)
+                assert abs(L - L_ref) <= 1e-12 * L_ref
+                assert np.max(np.abs(inner(gT) - inner(gT_ref))) <= 1e-12 * np.max(np.abs(inner(gT_ref))), sched
+                assert np.max(np.abs(inner(gC) - inner(gC_ref))) <= 1e-12 * np.max(np.abs(inner(gC_ref))), sched
+
+
 def test_autograd_function_matches_sweep():
     say("autograd")
     n = (36, 30, 28)

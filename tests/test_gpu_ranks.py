@@ -225,3 +225,38 @@ def test_flux_ranks_equal_global_block(n, dims, periods, ol):
                 assert np.array_equal(host(lps[r]), _block(glob_l, c, n, ol)), (split, r)
                 assert np.array_equal(host(gs[r])[1:-1, 1:-1, 1:-1],
                                       _block(glob_g, c, n, ol)[1:-1, 1:-1, 1:-1]), (split, r)
+
+
+@pytest.mark.parametrize("n,dims,periods", [((12, 10, 9), (2, 2, 2), (1, 1, 1)), ((11, 9, 10), (3, 1, 2), (1, 0, 1)),
+                                            ((40, 30, 24), (2, 1, 2), (1, 1, 1))])
+def test_checkpointed_gradient_on_ranks_equals_global_block(n, dims, periods):
+    """The checkpointed sweep over virtual ranks (snapshots every 3 steps)
+    gives the global block's gradients bit for bit on every block's inner
+    points, and its loss to the reduction order."""
+    ol = (2, 2, 2)
+    N = _global_n(n, ol, dims)
+    rng = np.random.default_rng(59)
+    T0, Ci, Tobs = (rng.uniform(0.3, 0.9, (N[2], N[1], N[0])) for _ in range(3))
+    for a in (T0, Ci, Tobs):
+        oracle.halo(a, ol, periods)
+    dx = 1.0 / (N[0] - 1)
+    dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
+    nt = 8
+    with grid(N, periods, ol):
+        say("gradient global block", N)
+        prob = diffusion.Problem(1.0, dt, dx, dx, dx, split=(4, 3, 3))
+        L, gT, gC, _ = diffusion.loss_and_grad(dev(T0), dev(Ci), dev(Tobs), prob, nt, ("periodic", 3))
+        gT, gC = host(gT), host(gC)
+    ranks = _ranks(dims)
+    with grid(n, periods, ol, dims=dims):
+        say("gradient ranks", n, dims, periods)
+        prob = diffusion.RankProblem(1.0, dt, dx, dx, dx, split=(4, 3, 3))
+        Lr, gTr, gCr, sw = diffusion.loss_and_grad_ranks([dev(_block(T0, c, n, ol)) for c in ranks],
+                                                         [dev(_block(Ci, c, n, ol)) for c in ranks],
+                                                         [dev(_block(Tobs, c, n, ol)) for c in ranks],
+                                                         prob, nt, ("periodic", 3))
+        assert sw.adjoints == nt
+        for r, c in enumerate(ranks):
+            for got, ref in ((gTr[r], gT), (gCr[r], gC)):
+                assert np.array_equal(host(got)[1:-1, 1:-1, 1:-1], _block(ref, c, n, ol)[1:-1, 1:-1, 1:-1]), r
+    assert abs(Lr - L) <= 1e-13 * L
