@@ -128,13 +128,17 @@ def test_split_equals_unsplit_bit_exact(dt_name):
             assert np.array_equal(o, outs[0])
 
 
-@pytest.mark.parametrize("n", [(260, 40, 20), (300, 35, 19)])
+@pytest.mark.parametrize("n", [(260, 40, 20), (300, 35, 19), (60, 30, 20), (131, 22, 18)])
 @pytest.mark.parametrize("dt_name", ["f64", "f32", "f16"])
-def test_wide_rows_split_forms(n, dt_name):
-    """Rows of a few hundred points: x slabs up to 31 points wide take the
-    64-point wrapped tiles, 32 to 64 points the 128-point wrapped tiles with
-    their outer x neighbours; every result equals the unsplit step, and FP64
-    the oracle."""
+@pytest.mark.parametrize("xform", ["fused", "halo"])
+def test_wide_rows_split_forms(n, dt_name, xform, monkeypatch):
+    """With the x exchange as a separate pass of the halo update the x slabs
+    are computed first: slabs up to 31 points wide take the 64-point wrapped
+    tiles, 32 to 64 points the 128-point wrapped tiles with their outer x
+    neighbours, rows below 64 points (or odd) the narrow tiles.  With the
+    fused exchange they join the inner launch.  Every result equals the
+    unsplit step, and FP64 the oracle."""
+    monkeypatch.setenv("IGG_X_EXCHANGE", xform)
     nx, ny, nz = n
     T0, Ci = synth.noisy_state_uniform_ci(nx, ny, nz, seed=19, noise=1e-2)
     oracle.halo(T0)
