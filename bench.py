@@ -15,9 +15,10 @@ value = T_eff = (bytes of T read + Ci read + T2 written, each once per point)
 
 Also reported on the same line:
   roofline      the inner-region step kernel: algorithmic bytes per launch
-                over its average duration, timed with HIP events on the
-                stream it runs on during a second pass of the same K steps,
-                against the 8 TB/s HBM3E peak;
+                over its average duration, timed live with HIP events on
+                the stream it runs on during a second timed pass of the same
+                K steps (so the events do not perturb `value`), against the
+                8 TB/s HBM3E peak;
   ms_per_step_samples
                 20 more timings of K steps: median and its 95% interval;
   cpu_baseline  the CPU oracle on the host cores: 100 steps of the same
@@ -91,12 +92,14 @@ def traffic_from_profiles(kernel_hash, key):
 
 
 def time_steps(igg, torch, T, W, C, lam, dt, dx, dy, dz, steps, warmup, split, rnd_seed=None):
-    """Warm up, then time `steps` diffusion steps twice: a plain pass (the
-    step time) and a pass with the library's kernel timing events on the
-    streams the kernels run on (the inner-kernel and boundary durations).
-    Returns (ms/step, final buffer of the plain pass, inner-kernel
-    ms/launch, inner points/launch, boundary-kernel ms per step, ms/step of
-    the instrumented pass)."""
+    """Do `warmup` untimed steps, then time exactly `steps` steps (the step
+    time); then time the same number of steps again with the library's
+    kernel timing events on the streams the kernels run on (HIP events,
+    live, in this process), which give the inner-kernel and boundary
+    durations without perturbing the first timing.  Returns (ms/step, final
+    buffer of the first timed pass, inner-kernel ms/launch, inner
+    points/launch, boundary-kernel ms per step, ms/step of the pass with the
+    kernel events)."""
     a, b = T, W
     it = 0
 
@@ -128,7 +131,7 @@ def time_steps(igg, torch, T, W, C, lam, dt, dx, dy, dz, steps, warmup, split, r
         # the instrumented pass continues from the final state in fresh buffers
         a, b = a.clone(), b.clone()
     igg.timing_read()  # discard
-    igg.timing_enable(True)
+    igg.timing_enable(True)  # the library makes its event pool here, before the pass
     ms_inst = timed()
     igg.timing_enable(False)
     k_ms, k_launches, k_points, b_ms = igg.timing_read()
@@ -258,7 +261,7 @@ def main():
         "halo_overhead": None,
         "ms_per_step_samples": samples,
         "boundary_ms_per_step": round(b_ms, 5),
-        "ms_per_step_instrumented": round(ms_inst, 5),
+        "ms_per_step_with_kernel_events": round(ms_inst, 5),
     }
 
     if args.profile:

@@ -336,14 +336,17 @@ int igg_reduce(int op, const igg_field *a, const igg_field *b, double *out, void
 int igg_plan_split(const int n[3], const int split[3], int boxes[7][6], int *nboxes);
 
 /* Kernel timing.  While enabled, each launch of the inner-region kernel of
- * diffusion_step / diffusion_step_adjoint (and the cell update of
+ * diffusion_step / diffusion_step_adjoint (and the fused pass of
  * diffusion_flux_step) is bracketed by two HIP events on the stream it runs
- * on, and so are the boundary-slab kernels of a split step.
+ * on, and so are the boundary-slab kernels of a split step.  The events
+ * carry no system-scope fence; enabling creates a pool of them for 1024
+ * launches on the current device, so timed work does not pay for their
+ * creation.
  * igg_timing_read synchronises those events and returns the summed
  * inner-kernel duration in milliseconds, its launch count, the inner points
  * those launches computed, and the summed boundary-kernel duration (any
  * pointer may be NULL), then resets the totals.  Errors: IGG_ERR_STATE,
- * IGG_ERR_HIP. */
+ * IGG_ERR_HIP (enabling makes the event pool, so it needs the GPU). */
 int igg_timing_enable(int on);
 int igg_timing_read(double *ms, int64_t *launches, int64_t *points, double *boundary_ms);
 

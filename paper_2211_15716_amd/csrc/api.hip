@@ -205,6 +205,9 @@ static int release_device()
     return rc;
 }
 
+// events made when timing is switched on: 1024 timed launches
+static const size_t kTimingPool = 2048;
+
 // Bracket a launch on stream s with timing events when timing is enabled;
 // kind 0 marks the inner-region kernel, kind 1 the boundary kernels.
 static int timing_mark(hipStream_t s, int kind)
@@ -989,6 +992,18 @@ int igg_timing_enable(int on)
     Grid &g = grid();
     if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
     g.timing = on != 0;
+    if (g.timing) {
+        // make the event pool now, so that timed work does not pay for
+        // creating events (it grows later if more launches are timed)
+        int rc;
+        if ((rc = ensure_device())) return rc;
+        while (g.tev.size() < kTimingPool) {
+            hipEvent_t e;
+            IGG_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+            g.tev.push_back(e);
+            g.tev_kind.push_back(0);
+        }
+    }
     return IGG_OK;
 }
 
