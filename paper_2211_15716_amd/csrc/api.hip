@@ -1,6 +1,8 @@
 // api.hip -- the extern "C" entry points of igg.h: argument checks (all on
-// the host, before any HIP call), the implicit global grid state and the
-// boundary-first schedule of the step.
+// the host, before any HIP call), the implicit global grid state (one rank,
+// or several virtual ranks as blocks on this device), the boundary-first
+// schedule of the steps, the time loop with its captured graph, and kernel
+// timing.
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -272,7 +274,7 @@ static int check_spacings(double lam, double dt, double dx, double dy, double dz
 // the update never reads the x slabs, so they join the inner launch and the
 // boundary phase is the y and z slabs.
 // boundary(r, slabs, stream) and inner(r, box, stream) launch rank r's
-// kernels; out holds the updated field of every rank.
+// kernels; out holds the nout updated fields of every rank, rank-major.
 template <typename BoundaryLaunch, typename InnerLaunch>
 static int run_split(const int *split, const igg_field *out, int nout, int halo_dims, BoundaryLaunch boundary,
                      InnerLaunch inner_launch, hipStream_t s)
