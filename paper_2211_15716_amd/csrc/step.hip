@@ -3,8 +3,9 @@
 //
 // Two kernels compute points, both through igg::diffuse, so a point's bits
 // do not depend on which of them computed it:
-//   k_step_boxes   one thread per point over up to six boxes (the boundary
-//                  slabs of the boundary-first schedule); plain global loads.
+//   k_step_boxes   one thread per point over up to six boxes (the y and z
+//                  boundary slabs, and any region too small for z-march
+//                  tiles); plain global loads.
 //   k_step_zmarch  the inner region and the x slabs: each work-group owns a
 //                  TW x TH tile of (x, y) columns and marches up a chunk of z
 //                  planes.  Every thread keeps T at k-1, k, k+1 (and k+2 in
@@ -13,6 +14,9 @@
 //                  y neighbours from there or from its own registers.  Thread
 //                  rows 0 and TY-1 also load the y-halo rows, lanes 0 and
 //                  BX-1 the x-halo points.
+// Both store the x halo of T2 as they compute the points the x exchange
+// moves (XHalo), and hash a point's global index for FP16 stochastic
+// rounding (SrOrigin).
 #include <stdlib.h>
 
 #include "host.hpp"
@@ -338,8 +342,9 @@ int launch_step_boxes(int dtype, const StepArgs &a, const Box *b, int nb, hipStr
 // Tile one or two boxes with TW x TH tiles and march zc planes per
 // work-group.  Chunks of 16 planes gave the best HBM throughput on MI355X
 // at 512^3 (many short marches balance the 256 CUs; the two extra planes
-// per chunk are mostly served from cache).  Keeping each x-row of tiles on
-// one XCD cut the inner kernel's L2 fetches by 10% and its time by 6%.
+// per chunk are mostly served from cache); smaller grids halve the chunk
+// (down to 4) to keep about 2048 work-groups.  Keeping each x-row of tiles
+// on one XCD cut the inner kernel's L2 fetches by 10% and its time by 6%.
 // Launch settings of one z-march launch: planes per work-group and the
 // work-group to XCD mapping, each with an environment override for tuning.
 struct ZLaunch {
@@ -416,7 +421,8 @@ static bool vec_ok(const StepArgs &a)
 // loads, two rows per thread, 16 rows.  FP16: 256-point (512-byte) rows,
 // 8-byte loads, 16 rows.
 // These shapes and work-group mappings measured fastest on MI355X at 512^3.
-// Rows whose length does not allow vector loads take one point per lane.
+// Rows whose length does not allow vector loads take one point per lane;
+// regions below zmarch_min_points() take the box kernel.
 int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s)
 {
     if (box_count(b) < zmarch_min_points()) return launch_step_boxes(dtype, a, &b, 1, s);
@@ -432,8 +438,10 @@ int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s)
     return run_zmarch<_Float16, 1, 64, 8, 2>(a, &b, 1, s, kInnerRanges);
 }
 
-// x slabs.  The end of row j-1 and the start of row j sit next to each
-// other in memory, so the two x slabs of neighbouring rows form one wrapped
+// x slabs (computed first only when the x exchange is a separate pass of
+// the halo update).  The end of row j-1 and the start of row j sit next to
+// each other in memory, so the two x slabs of neighbouring rows form one
+// wrapped
 // tile of 2*W2 points (W2 = 32 or 64): one contiguous run per row pair and
 // plane holding every x neighbour, instead of two narrow pieces plus two
 // separate halo lines.  Wider slabs or short rows take narrow 16-point
