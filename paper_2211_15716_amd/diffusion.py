@@ -81,11 +81,16 @@ class FluxProblem:
         self.split = split
         self._q = None
 
+    @staticmethod
+    def face_arrays(T):
+        """Zeroed face-flux arrays qx (nx+1 faces in x), qy, qz for a cell field T."""
+        nz, ny, nx = T.shape
+        shapes = [(nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx)]
+        return [torch.zeros(s, dtype=T.dtype, device=T.device) for s in shapes]
+
     def _faces(self, T):
         if self._q is None:
-            nz, ny, nx = T.shape
-            shapes = [(nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx)]
-            self._q = [torch.zeros(s, dtype=T.dtype, device=T.device) for s in shapes]
+            self._q = self.face_arrays(T)
         return self._q
 
     def step(self, out, T, Ci, stream=None):
@@ -115,6 +120,27 @@ class RankProblem(Problem):
     def adjoint(self, lam_n, lam_np1, Tn, Ci, gCi, stream=None):
         igg.diffusion_step_adjoint_ranks(lam_n, lam_np1, Tn, Ci, gCi, self.lam, self.dt, self.dx, self.dy, self.dz,
                                          split=self.split, stream=stream)
+
+
+class FluxRankProblem(FluxProblem):
+    """The staggered flux form on a grid of virtual ranks: states, Ci and
+    gradients are lists with one block per rank, the face fluxes one
+    (qx, qy, qz) triple per rank (`fluxes`), and the steps go through
+    diffusion_flux_step_ranks / diffusion_flux_step_adjoint_ranks."""
+
+    def _faces(self, Ts):
+        if self._q is None:
+            self._q = [self.face_arrays(T) for T in Ts]
+        return self._q
+
+    def step(self, out, T, Ci, stream=None):
+        q = self._faces(T)
+        igg.diffusion_flux_step_ranks(out, T, Ci, [x[0] for x in q], [x[1] for x in q], [x[2] for x in q],
+                                      self.lam, self.dt, self.dx, self.dy, self.dz, split=self.split, stream=stream)
+
+    def adjoint(self, lam_n, lam_np1, Tn, Ci, gCi, stream=None):
+        igg.diffusion_flux_step_adjoint_ranks(lam_n, lam_np1, Tn, Ci, gCi, self.lam, self.dt, self.dx, self.dy,
+                                              self.dz, split=self.split, stream=stream)
 
 
 # states are tensors, or lists of per-rank blocks on a grid of virtual ranks
@@ -259,6 +285,47 @@ class DiffusionSolve(torch.autograd.Function):
         return _inner_only(gT0), _inner_only(gCi), None, None, None
 
 
+def _need_unit_overlaps(what):
+    # with overlaps of 2 the blocks' inner points tile the global grid's
+    # unique points, so a loss over every block's inner points counts each
+    # unique point once
+    if tuple(igg.topology()["overlaps"]) != (2, 2, 2):
+        raise ValueError(what + " needs overlaps (2, 2, 2)")
+
+
+class DiffusionSolveRanks(torch.autograd.Function):
+    """DiffusionSolve on a grid of virtual ranks.
+
+    apply(prob, nt, schedule, *blocks) -- blocks are the P blocks of T0
+    followed by the P blocks of Ci (P = igg.nranks(), rank order), each with
+    a valid halo; prob is a RankProblem or FluxRankProblem.  Returns the P
+    blocks of T_nt.  The gradients (P blocks of dL/dT0, then P of dL/dCi)
+    are zero on halo points: the loss may only depend on the blocks' inner
+    points, which tile the global unique points (overlaps of 2 only)."""
+
+    @staticmethod
+    def forward(ctx, prob, nt, schedule, *blocks):
+        from . import checkpoint
+        P = igg.nranks()
+        if len(blocks) != 2 * P:
+            raise ValueError(f"expected {2 * P} blocks (T0 and Ci of {P} ranks), got {len(blocks)}")
+        _need_unit_overlaps("DiffusionSolveRanks")
+        ops = checkpoint.make(schedule[0], nt, schedule[1] if len(schedule) > 1 else None)
+        sweep = Sweep(prob, [b.detach() for b in blocks[P:]], [b.detach() for b in blocks[:P]], ops)
+        out = sweep.forward(nt)
+        ctx.sweep = sweep
+        return tuple(out)
+
+    @staticmethod
+    def backward(ctx, *gs):
+        sweep = ctx.sweep
+        lam_nt = [_inner_only(g.contiguous()) for g in gs]
+        igg.update_halo_ranks(*[(t,) for t in lam_nt])
+        gT0, gCi = sweep.reverse(lam_nt)
+        ctx.sweep = None
+        return (None, None, None, *[_inner_only(t) for t in gT0], *[_inner_only(t) for t in gCi])
+
+
 def loss_and_grad(T0, Ci, T_obs, prob, nt, schedule=("store_all",)):
     """0.5*||T_nt - T_obs||^2 over the unique points (FP64 reduction on the
     GPU) and its gradients (dL/dT0, dL/dCi), by DiffusionSolve."""
@@ -275,12 +342,11 @@ def loss_and_grad(T0, Ci, T_obs, prob, nt, schedule=("store_all",)):
 
 def loss_and_grad_ranks(T0s, Cis, T_obs_s, prob, nt, schedule=("store_all",)):
     """loss_and_grad on a grid of virtual ranks (lists of per-rank blocks,
-    prob a RankProblem).  The blocks' inner points tile the global grid's
-    unique points when the overlaps are 2, so the loss is the sum of the
-    blocks' FP64 sums; other overlaps are refused."""
+    prob a RankProblem or FluxRankProblem).  The blocks' inner points tile
+    the global grid's unique points when the overlaps are 2, so the loss is
+    the sum of the blocks' FP64 sums; other overlaps are refused."""
     from . import checkpoint
-    if tuple(igg.topology()["overlaps"]) != (2, 2, 2):
-        raise ValueError("loss_and_grad_ranks needs overlaps (2, 2, 2)")
+    _need_unit_overlaps("loss_and_grad_ranks")
     ops = checkpoint.make(schedule[0], nt, schedule[1] if len(schedule) > 1 else None)
     sweep = Sweep(prob, Cis, T0s, ops)
     Tnt = sweep.forward(nt)

@@ -247,3 +247,27 @@ def test_virtual_ranks_cover_the_global_grid():
         assert (cover == 2).sum() == (dims - 1) * ol
         # unique points: N minus the ol periodic images when periodic
         assert N - ol * per == oracle.global_size((n, n, n), (dims, 1, 1), (per, 0, 0), (ol, ol, ol))[0]
+
+
+def test_rank_solvers_check_block_count_and_overlaps(host_grid):
+    """DiffusionSolveRanks and loss_and_grad_ranks refuse, before any GPU
+    work, a block count other than 2 x nranks and overlaps other than 2 (with
+    wider overlaps the blocks' inner points share points, so a loss over
+    them would count some unique points twice)."""
+    torch = pytest.importorskip("torch")
+    from paper_2211_15716_amd import diffusion
+    t = torch.zeros(1)
+    igg.init_global_grid(10, 8, 7, dims=(2, 1, 1), periods=(1, 1, 1), overlaps=(2, 2, 2))
+    try:
+        with pytest.raises(ValueError, match="expected 4 blocks"):
+            diffusion.DiffusionSolveRanks.apply(None, 2, ("store_all",), t, t, t)
+    finally:
+        igg.finalize_global_grid()
+    igg.init_global_grid(10, 8, 7, dims=(2, 1, 1), periods=(1, 1, 1), overlaps=(3, 2, 2))
+    try:
+        with pytest.raises(ValueError, match="overlaps"):
+            diffusion.DiffusionSolveRanks.apply(None, 2, ("store_all",), t, t, t, t)
+        with pytest.raises(ValueError, match="overlaps"):
+            diffusion.loss_and_grad_ranks([t, t], [t, t], [t, t], None, 2)
+    finally:
+        igg.finalize_global_grid()

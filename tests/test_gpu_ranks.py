@@ -260,3 +260,93 @@ def test_checkpointed_gradient_on_ranks_equals_global_block(n, dims, periods):
             for got, ref in ((gTr[r], gT), (gCr[r], gC)):
                 assert np.array_equal(host(got)[1:-1, 1:-1, 1:-1], _block(ref, c, n, ol)[1:-1, 1:-1, 1:-1]), r
     assert abs(Lr - L) <= 1e-13 * L
+
+
+def _grad_problem(N, periods, seed):
+    ol = (2, 2, 2)
+    rng = np.random.default_rng(seed)
+    T0, Ci, Tobs = (rng.uniform(0.3, 0.9, (N[2], N[1], N[0])) for _ in range(3))
+    for a in (T0, Ci, Tobs):
+        oracle.halo(a, ol, periods)
+    return T0, Ci, Tobs
+
+
+@pytest.mark.parametrize("n,dims,periods,split", [((12, 10, 9), (2, 2, 2), (1, 1, 1), None),
+                                                  ((11, 9, 10), (3, 1, 2), (1, 0, 1), (4, 3, 3)),
+                                                  ((20, 16, 14), (2, 1, 2), (1, 1, 0), (4, 3, 3))])
+def test_flux_checkpointed_gradient_on_ranks_equals_global_block(n, dims, periods, split):
+    """The checkpointed sweep of the staggered flux form over virtual ranks
+    (snapshots every 3 steps) gives the global block's gradients bit for bit
+    on every block's inner points, and its loss to the reduction order."""
+    ol = (2, 2, 2)
+    N = _global_n(n, ol, dims)
+    T0, Ci, Tobs = _grad_problem(N, periods, 61)
+    dx = 1.0 / (N[0] - 1)
+    dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
+    nt = 7
+    with grid(N, periods, ol):
+        say("flux gradient global block", N, split)
+        prob = diffusion.FluxProblem(1.0, dt, dx, dx, dx, split=split)
+        L, gT, gC, _ = diffusion.loss_and_grad(dev(T0), dev(Ci), dev(Tobs), prob, nt, ("periodic", 3))
+        gT, gC = host(gT), host(gC)
+    ranks = _ranks(dims)
+    with grid(n, periods, ol, dims=dims):
+        say("flux gradient ranks", n, dims, periods, split)
+        prob = diffusion.FluxRankProblem(1.0, dt, dx, dx, dx, split=split)
+        Lr, gTr, gCr, sw = diffusion.loss_and_grad_ranks([dev(_block(T0, c, n, ol)) for c in ranks],
+                                                         [dev(_block(Ci, c, n, ol)) for c in ranks],
+                                                         [dev(_block(Tobs, c, n, ol)) for c in ranks],
+                                                         prob, nt, ("periodic", 3))
+        assert sw.adjoints == nt
+        for r, c in enumerate(ranks):
+            for got, ref in ((gTr[r], gT), (gCr[r], gC)):
+                assert np.array_equal(host(got)[1:-1, 1:-1, 1:-1], _block(ref, c, n, ol)[1:-1, 1:-1, 1:-1]), r
+    assert abs(Lr - L) <= 1e-13 * L
+
+
+@pytest.mark.parametrize("form", ["laplacian", "flux"])
+@pytest.mark.parametrize("n,dims,periods", [((12, 10, 9), (2, 2, 2), (1, 1, 1)),
+                                            ((11, 9, 10), (3, 1, 2), (1, 0, 1))])
+def test_diffusion_solve_ranks_autograd_equals_global(n, dims, periods, form):
+    """torch.autograd through DiffusionSolveRanks (loss over the blocks'
+    inner points, written in torch) gives the global DiffusionSolve's
+    T_nt and gradients bit for bit on every block's inner points."""
+    ol = (2, 2, 2)
+    N = _global_n(n, ol, dims)
+    T0, Ci, Tobs = _grad_problem(N, periods, 67)
+    dx = 1.0 / (N[0] - 1)
+    dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
+    nt = 6
+    sched = ("binomial", 2)
+    single = diffusion.Problem if form == "laplacian" else diffusion.FluxProblem
+    multi = diffusion.RankProblem if form == "laplacian" else diffusion.FluxRankProblem
+    split = (4, 3, 3)
+
+    def loss(T, O):
+        d = T[1:-1, 1:-1, 1:-1] - O[1:-1, 1:-1, 1:-1]
+        return 0.5 * (d * d).sum()
+
+    with grid(N, periods, ol):
+        say("solve global block", form, N)
+        T, C = dev(T0).requires_grad_(), dev(Ci).requires_grad_()
+        out = diffusion.DiffusionSolve.apply(T, C, single(1.0, dt, dx, dx, dx, split=split), nt, sched)
+        loss(out, dev(Tobs)).backward()
+        g_out, gT, gC = host(out), host(T.grad), host(C.grad)
+    ranks = _ranks(dims)
+    with grid(n, periods, ol, dims=dims):
+        say("solve ranks", form, n, dims, periods)
+        Ts = [dev(_block(T0, c, n, ol)).requires_grad_() for c in ranks]
+        Cs = [dev(_block(Ci, c, n, ol)).requires_grad_() for c in ranks]
+        outs = diffusion.DiffusionSolveRanks.apply(multi(1.0, dt, dx, dx, dx, split=split), nt, sched, *Ts, *Cs)
+        assert len(outs) == len(ranks)
+        sum(loss(o, dev(_block(Tobs, c, n, ol))) for o, c in zip(outs, ranks)).backward()
+        for r, c in enumerate(ranks):
+            assert np.array_equal(host(outs[r]), _block(g_out, c, n, ol)), r
+            for got, ref in ((Ts[r].grad, gT), (Cs[r].grad, gC)):
+                assert np.array_equal(host(got), _block(ref, c, n, ol) * _inner_mask(n)), r
+
+
+def _inner_mask(n):
+    m = np.zeros((n[2], n[1], n[0]))
+    m[1:-1, 1:-1, 1:-1] = 1.0
+    return m
