@@ -185,8 +185,9 @@ int igg_finalize_global_grid(void);
  *          while the inner region runs on `stream`, which finally waits for
  *          the helper.  The x exchange is stored by the step kernels as they
  *          compute the points it moves, so the x slabs are computed with the
- *          inner region.  Inner regions below 2^21 points run slabs, update
- *          and inner region as one chain on `stream` (launch-bound sizes).
+ *          inner region.  Inner regions below 2^21 points, and FP16 fields
+ *          (whose kernels are partly ALU-bound), run slabs, update and inner
+ *          region as one chain on `stream`.
  *          NULL = no overlap: everything runs on `stream` in order.
  *   rnd    FP16 store rounding, NULL = round to nearest even (ignored for
  *          FP64/FP32).

@@ -270,7 +270,9 @@ static int check_spacings(double lam, double dt, double dx, double dy, double dz
 // large inner regions take schedule 1; small grids are launch-bound, the
 // cross-stream fork and join cost more than the update they would hide, and
 // a captured graph of a single chain replays fastest, so they take schedule
-// 2.  When the x exchange is fused into the stores (or x is not periodic)
+// 2.  FP16 fields take schedule 2 at any size: their kernels are partly
+// bound by the vector ALU (stochastic rounding), and slabs running beside
+// the inner region made the 512^3 step 7% slower than the serial chain.  When the x exchange is fused into the stores (or x is not periodic)
 // the update never reads the x slabs, so they join the inner launch and the
 // boundary phase is the y and z slabs.
 // boundary(r, slabs, stream) and inner(r, box, stream) launch rank r's
@@ -295,7 +297,8 @@ static int run_split(const int *split, const igg_field *out, int nout, int halo_
         inner.i0 = 1;
         inner.i1 = g.n[0] - 1;
     }
-    const int sched = g.schedule >= 0 ? g.schedule : (box_points(inner) >= kSideMinPoints ? 1 : 2);
+    const bool side_pays = box_points(inner) >= kSideMinPoints && out[0].dtype != IGG_F16;
+    const int sched = g.schedule >= 0 ? g.schedule : (side_pays ? 1 : 2);
     const bool on_side = sched == 1, serial = sched == 2;
     hipStream_t bs = on_side ? g.side : s;
     if (on_side) {

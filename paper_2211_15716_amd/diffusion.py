@@ -164,22 +164,39 @@ def _copy_(dst, src):
         dst.copy_(src)
 
 
+def _fuse_stores(ops):
+    """Merge ("advance", a, b) followed by ("store", b) into
+    ("advance_store", a, b): the last step then writes the snapshot itself
+    instead of a work buffer that is copied afterwards."""
+    out = []
+    for op in ops:
+        if op[0] == "store" and out and out[-1][0] == "advance" and out[-1][2] == op[1] and op[1] > out[-1][1]:
+            out[-1] = ("advance_store", out[-1][1], op[1])
+        else:
+            out.append(op)
+    return out
+
+
 class Sweep:
     """Runs a checkpointing schedule (paper_2211_15716_amd.checkpoint) on the
     GPU.  Snapshots are device tensors (lists of per-rank blocks with a
     RankProblem); the current state is either a snapshot (read only) or one
-    of two work buffers, so advancing never overwrites a snapshot.  Counts
-    forward and adjoint steps."""
+    of two work buffers, so advancing never overwrites a snapshot.  A state
+    that is stored right after it is computed is computed into its snapshot
+    buffer directly, which is a freed snapshot's buffer when one is free (its
+    halo planes in non-periodic dimensions hold T0's, which no step writes).
+    Counts forward and adjoint steps."""
 
     def __init__(self, prob, Ci, T0, ops):
         self.p, self.Ci, self.ops = prob, Ci, ops
         self.store = {0: T0}
         self.work = [_clone(T0), _clone(T0)]  # halo planes of non-periodic dimensions
+        self.pool = []  # buffers of freed snapshots
         self.cur, self.cur_n = T0, 0
         self.advances = 0
         self.adjoints = 0
         self.peak = 1
-        self.fwd, self.rev = _split_ops(ops)
+        self.fwd, self.rev = _split_ops(_fuse_stores(ops))
 
     def _advance(self, a, b):
         assert self.cur_n == a, (a, self.cur_n)
@@ -196,13 +213,28 @@ class Sweep:
             self.cur, self.cur_n = self.store[op[1]], op[1]
         elif kind == "advance":
             self._advance(op[1], op[2])
+        elif kind == "advance_store":
+            a, b = op[1], op[2]
+            self._advance(a, b - 1)
+            dst = None
+            for q, buf in enumerate(self.pool):
+                if buf is not self.cur:
+                    dst = self.pool.pop(q)
+                    break
+            if dst is None:
+                dst = _clone(self.cur)
+            self.p.step(dst, self.cur, self.Ci)
+            self.advances += 1
+            self.cur, self.cur_n = dst, b
+            self.store[b] = dst
+            self.peak = max(self.peak, len(self.store))
         elif kind == "store":
             assert self.cur_n == op[1]
             self.store[op[1]] = _clone(self.cur)
             self.peak = max(self.peak, len(self.store))
         elif kind == "free":
-            if op[1] != 0:
-                del self.store[op[1]]
+            if op[1] != 0:  # T0 is the caller's tensor
+                self.pool.append(self.store.pop(op[1]))
         else:
             raise ValueError(op)
 

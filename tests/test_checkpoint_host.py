@@ -120,3 +120,73 @@ def test_schedule_reproduces_store_all_gradient(sched):
     lp, g = _run_schedule_on_oracle(ck.make(sched[0], nt, sched[1]), T0, Ci, Tobs, nt, 1.0, dt, d)
     assert np.array_equal(oracle.inner(lp), oracle.inner(gT))
     assert np.array_equal(oracle.inner(g), oracle.inner(gC))
+
+
+class _RecordingProblem:
+    """A stand-in for the GPU problem, on CPU tensors: the step writes only
+    the inner points (T2 = 0.5*T + Ci, halo planes untouched, like the halo
+    planes of non-periodic dimensions) and checks that the buffer it writes
+    carries T0's halo planes; the adjoint records the state it is given."""
+
+    def __init__(self, T0):
+        import torch
+        self.mask = torch.ones_like(T0, dtype=torch.bool)
+        self.mask[1:-1, 1:-1, 1:-1] = False
+        self.halo = T0[self.mask].clone()
+        self.seen = []
+
+    def step(self, out, T, Ci, stream=None):
+        assert out is not T
+        assert bool((out[self.mask] == self.halo).all())
+        out[1:-1, 1:-1, 1:-1] = 0.5 * T[1:-1, 1:-1, 1:-1] + Ci[1:-1, 1:-1, 1:-1]
+
+    def adjoint(self, lam_n, lam_np1, Tn, Ci, gCi, stream=None):
+        self.seen.append(Tn.clone())
+        lam_n.copy_(lam_np1)
+
+
+@pytest.mark.parametrize("sched", [("store_all",), ("periodic", 3), ("periodic", 16), ("sqrt",), ("binomial", 1),
+                                   ("binomial", 2), ("binomial", 4)])
+@pytest.mark.parametrize("nt", [1, 2, 7, 20])
+def test_sweep_executes_schedule_on_buffers(sched, nt):
+    """The GPU driver's executor (Sweep, with snapshots written in place
+    and freed buffers reused) run on CPU tensors: the forward result is the
+    direct loop's, every adjoint step sees its state T_n, T0 is never
+    written, the step count is the schedule's, and no more buffers are made
+    than the schedule's peak number of snapshots."""
+    torch = pytest.importorskip("torch")
+    from paper_2211_15716_amd import diffusion
+    rng = np.random.default_rng(nt)
+    T0 = torch.from_numpy(rng.uniform(0.0, 1.0, (5, 6, 7)))
+    Ci = torch.from_numpy(rng.uniform(0.0, 1.0, (5, 6, 7)))
+    T0_copy = T0.clone()
+    states = [T0.clone()]
+    for _ in range(nt):
+        nxt = states[-1].clone()
+        nxt[1:-1, 1:-1, 1:-1] = 0.5 * states[-1][1:-1, 1:-1, 1:-1] + Ci[1:-1, 1:-1, 1:-1]
+        states.append(nxt)
+    prob = _RecordingProblem(T0)
+    ops = ck.make(sched[0], nt, sched[1] if len(sched) > 1 else None)
+    made = []
+    real_clone = diffusion._clone
+
+    def counting_clone(x):
+        y = real_clone(x)
+        made.append(y)
+        return y
+
+    diffusion._clone = counting_clone
+    try:
+        sw = diffusion.Sweep(prob, Ci, T0, ops)
+        out = sw.forward(nt)
+        assert torch.equal(out, states[nt])
+        sw.reverse(torch.zeros_like(T0))
+    finally:
+        diffusion._clone = real_clone
+    assert torch.equal(T0, T0_copy)
+    assert len(prob.seen) == nt
+    for q, seen in enumerate(prob.seen):
+        assert torch.equal(seen, states[nt - 1 - q]), q
+    assert sw.advances == sum(op[2] - op[1] for op in ops if op[0] == "advance") + 1
+    # two work buffers, the forward result, and at most peak-1 snapshot buffers
+    assert len(made) <= 3 + sw.peak - 1
