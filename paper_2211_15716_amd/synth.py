@@ -85,6 +85,50 @@ def fourier_mode(nx, ny, nz, m=(1, 1, 1), A=1.7, B=0.1):
     return A + B * (c(nz, m[2])[:, None, None] * c(ny, m[1])[None, :, None] * c(nx, m[0])[None, None, :])
 
 
+# --------------------------------------------------------------------------- hashed fields
+# Fields too large to draw on the host (billions of points): each point's
+# value is offset + u, u = h * 2^-32 in [0, 1), where h is a 32-bit integer
+# hash of the point's linear index (x fastest) xor a seed -- two rounds of
+# x = ((x >> 16) ^ x) * 0x45d9f3b mod 2^32, then x ^= x >> 16 (Thomas
+# Mueller's public-domain integer hash).  Every product stays below 2^59, so
+# int64 arithmetic is exact on numpy and torch alike, and the same values
+# come out on the device (whole field) and on the host (any chosen points).
+_M32 = 0xFFFFFFFF
+_HK = 0x45D9F3B
+
+
+def _hash32(x):
+    x = (((x >> 16) ^ x) * _HK) & _M32
+    x = (((x >> 16) ^ x) * _HK) & _M32
+    return (x >> 16) ^ x
+
+
+def hashed_uniform(index, seed):
+    """u in [0, 1) for linear indices (numpy, each below 2^32)."""
+    x = (np.asarray(index, dtype=np.int64) ^ np.int64(seed)) & _M32
+    return _hash32(x).astype(np.float64) * 2.0 ** -32
+
+
+def hashed_field_torch(nx, ny, nz, seed, offset, device, planes=64):
+    """offset + u at every point of an (nz, ny, nx) float64 torch tensor on
+    `device`, made plane block by plane block (the values equal
+    offset + hashed_uniform(i + nx*(j + ny*k), seed))."""
+    import torch
+    if nx * ny * nz >= 1 << 32:
+        raise ValueError("hashed fields index at most 2^32 points")
+    out = torch.empty((nz, ny, nx), dtype=torch.float64, device=device)
+    plane = nx * ny
+    base = torch.arange(plane, dtype=torch.int64, device=device)
+    for k0 in range(0, nz, planes):
+        k1 = min(nz, k0 + planes)
+        ks = torch.arange(k0, k1, dtype=torch.int64, device=device)
+        x = ((base[None, :] + ks[:, None] * plane) ^ seed) & _M32
+        u = _hash32(x).to(torch.float64) * 2.0 ** -32
+        out[k0:k1] = (u + offset).view(k1 - k0, ny, nx)
+        del x, u
+    return out
+
+
 # --------------------------------------------------------------------------- named workloads
 def workload(name, seed=0, n=None):
     """The named workloads of the diffusion study.

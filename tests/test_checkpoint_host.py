@@ -190,3 +190,25 @@ def test_sweep_executes_schedule_on_buffers(sched, nt):
     assert sw.advances == sum(op[2] - op[1] for op in ops if op[0] == "advance") + 1
     # two work buffers, the forward result, and at most peak-1 snapshot buffers
     assert len(made) <= 3 + sw.peak - 1
+
+
+def test_hashed_fields_agree_between_host_and_torch():
+    """The hashed input fields (made whole on the device, recomputed point by
+    point on the host for the sampled parity checks of fields beyond 2^31
+    points) agree bit for bit between torch and numpy, match the hash written
+    out in plain Python integers, and fill [offset, offset + 1)."""
+    torch = pytest.importorskip("torch")
+    t = synth.hashed_field_torch(9, 7, 5, 23, 0.5, "cpu", planes=2)
+    idx = np.arange(9 * 7 * 5).reshape(5, 7, 9)
+    assert np.array_equal(t.numpy(), 0.5 + synth.hashed_uniform(idx, 23))
+
+    def plain(v):
+        for _ in range(2):
+            v = (((v >> 16) ^ v) * 0x45D9F3B) % (1 << 32)
+        return (v >> 16) ^ v
+
+    big = [0, 1, 77, (1 << 31) - 1, 1 << 31, (1 << 31) + 12345, (1 << 32) - 1]
+    want = [plain((i ^ 23) % (1 << 32)) / 2.0 ** 32 for i in big]
+    assert np.array_equal(synth.hashed_uniform(big, 23), np.array(want))
+    u = synth.hashed_uniform(np.arange(1 << 16), 5)
+    assert u.min() >= 0.0 and u.max() < 1.0 and abs(u.mean() - 0.5) < 0.01

@@ -226,3 +226,47 @@ def test_fp16_stochastic_rounding_is_unbiased_and_deterministic():
         igg.diffusion_step(rn, T16, C16, 1.0, dt, dx, dx, dx, split=None)
         torch.cuda.synchronize()
         assert not torch.equal(rn, outs[0])
+
+
+def _hashed_box(c, r, n, seed, offset):
+    """Values of a periodic hashed field (overlap 2, halo = periodic images)
+    on the padded index box c-r .. c+r around point c = (i, j, k)."""
+    ax = [(np.arange(cd - r, cd + r + 1) - 1) % (nd - 2) + 1 for cd, nd in zip(c, n)]
+    lin = ax[0][None, None, :] + n[0] * (ax[1][None, :, None] + n[1] * ax[2][:, None, None])
+    return offset + synth.hashed_uniform(lin, seed)
+
+
+def test_fp64_step_beyond_2_31_points_matches_oracle():
+    """A grid of 1024 x 1024 x 2052 = 2.15e9 points (more than 2^31, so
+    element indices need 64 bits; 17 GB per FP64 field), hashed uniform T in
+    [1.5, 2.5) and Ci in [0.5, 1.5): two boundary-first steps, then sampled
+    points -- among them points whose linear index exceeds 2^31 -- against
+    the oracle's light cone, <= 1e-12 relative, and the halo planes of the
+    result equal to their periodic images."""
+    n = (1024, 1024, 2052)
+    assert n[0] * n[1] * n[2] > 1 << 31
+    lam, nt = 1.0, 2
+    d = tuple(1.0 / (m - 1) for m in n)
+    dt = oracle.time_step(*d, lam, 1.5)  # Ci < 1.5 everywhere
+    pts = [(1, 1, 1), (1022, 1022, 2050), (700, 1000, 2049), (3, 2, 2050), (1022, 511, 2048), (512, 512, 1024),
+           (16, 17, 2047), (1007, 1021, 2050)]
+    assert max(i + n[0] * (j + n[1] * k) for i, j, k in pts) > 1 << 31
+    say("fp64 beyond 2^31 points", n)
+    with grid(n, zmarch_min=None):
+        T = synth.hashed_field_torch(*n, 1, 1.5, "cuda")
+        C = synth.hashed_field_torch(*n, 2, 0.5, "cuda")
+        igg.update_halo(T, C)
+        out = diffusion.forward(T, C, nt, lam, dt, *d, split=(16, 2, 2))
+        got = np.array([out[k, j, i].item() for (i, j, k) in pts])
+        assert torch.equal(out[0], out[-2]) and torch.equal(out[-1], out[1])
+        assert torch.equal(out[:, 0], out[:, -2]) and torch.equal(out[:, -1], out[:, 1])
+        assert torch.equal(out[:, :, 0], out[:, :, -2]) and torch.equal(out[:, :, -1], out[:, :, 1])
+        del T, C, out
+    ref = []
+    for c in pts:
+        Tb = _hashed_box(c, nt, n, 1, 1.5)
+        Cb = _hashed_box(c, nt, n, 2, 0.5)
+        ref.append(oracle.run(Tb, Cb, nt, lam, dt, *d, ol=(2, 2, 2), periods=(0, 0, 0))[nt, nt, nt])
+    ref = np.array(ref)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    assert err <= 1e-12, err
