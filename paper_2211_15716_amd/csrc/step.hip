@@ -97,6 +97,7 @@ struct ZTile {
     int nx, ny;   // array sizes in x and y
     int zc;       // planes per work-group
     int remap;    // XCD-aware renumbering of work-groups
+    int rblock;   // mode 2: x-rows of tiles per block dealt to one XCD
     // wrapped x-slab tiles (WRAP): virtual row j holds the last w2 points of
     // row j-1 and the first w2 points of row j, which sit next to each other
     // in memory; points of the left part are computed where x is in
@@ -132,12 +133,12 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
         // keep each x-row of tiles on one XCD (work-group g runs on XCD g % 8),
         // so neighbouring tiles read each other's edge lines from the same L2;
         // mode 2 deals rows to XCDs in turn, mode 3 in contiguous ranges
-        const int64_t ntx0 = z.box[0].ntx;
-        const int64_t P = gridDim.x / ntx0, P8 = P / 8 * 8;
+        const int64_t ntx0 = z.box[0].ntx, B = z.rblock;
+        const int64_t P = gridDim.x / ntx0, P8 = z.remap == 2 ? P / (8 * B) * (8 * B) : P / 8 * 8;
         if (g < ntx0 * P8) {
             const int64_t x = g % 8, slot = g / 8;
             const int64_t q = slot / ntx0;
-            const int64_t p = z.remap == 2 ? x + 8 * q : x * (P8 / 8) + q;
+            const int64_t p = z.remap == 2 ? ((q / B) * 8 + x) * B + q % B : x * (P8 / 8) + q;
             g = slot % ntx0 + ntx0 * p;
         }
     }
@@ -383,6 +384,7 @@ static int run_zmarch(const StepArgs &a, const Box *b, int nbox, hipStream_t s, 
     if (zc < 1) zc = auto_zchunk(columns, depth_max, L.zc);
     z.zc = zc;
     z.remap = env_int(L.remap_env, L.remap);
+    z.rblock = std::max(1, env_int("IGG_XCD_BLOCK", 1));
     int64_t blocks = 0;
     z.split_block = INT64_MAX;
     for (int q = 0; q < nbox; ++q) {
