@@ -30,6 +30,15 @@
  *     GPU, and released by igg_finalize_global_grid.  Calls that overlap in
  *     time (from several host threads, or on unordered streams) race on the
  *     shared halo buffers and are not supported.
+ *   - Environment variables choose schedules and launch shapes only; no
+ *     setting changes a result bit.  Read by igg_init_global_grid:
+ *     IGG_SCHEDULE (0, 1 or 2: see diffusion_step; unset = by size and
+ *     type), IGG_X_EXCHANGE ("halo": x slabs and an x pass of the halo
+ *     update instead of the x exchange stored by the step kernels),
+ *     IGG_ZMARCH_MIN_POINTS (smallest region for the z-march kernels).
+ *     Read at each launch (tuning): IGG_ZCHUNK, IGG_XCD_REMAP,
+ *     IGG_XCD_BLOCK, IGG_XSLAB_ZCHUNK, IGG_XSLAB_REMAP, IGG_ADJ_ZCHUNK,
+ *     IGG_ADJ_REMAP, IGG_ADJ_XCD_BLOCK, IGG_FLUX_ZCHUNK, IGG_FLUX_REMAP.
  */
 #ifndef IGG_MI355X_H
 #define IGG_MI355X_H

@@ -669,7 +669,8 @@ int igg_init_global_grid(int nx, int ny, int nz, const int dims[3], const int pe
     g.timing = false;
     {
         const char *e = getenv("IGG_SCHEDULE");
-        g.schedule = (e && *e) ? atoi(e) : -1;
+        const int sv = (e && *e) ? atoi(e) : -1;
+        g.schedule = (sv >= 0 && sv <= 2) ? sv : -1;  // anything else: chosen by size and type
         const char *x = getenv("IGG_X_EXCHANGE");
         g.fuse_x = !(x && strcmp(x, "halo") == 0);
         const char *zm = getenv("IGG_ZMARCH_MIN_POINTS");
