@@ -345,7 +345,7 @@ static int run_zmarch(const AdjArgs &a, const Box &b, hipStream_t s)
     z.nty = (b.j1 - b.j0 + TH - 1) / TH;
     int depth = b.k1 - b.k0;
     int zc = env_int("IGG_ADJ_ZCHUNK", 0);
-    if (zc < 1) zc = auto_zchunk((int64_t)z.ntx * z.nty, depth, 16);
+    if (zc < 1) zc = zchunk_for_groups((int64_t)z.ntx * z.nty, depth, 16);
     z.zc = zc;
     z.remap = env_int("IGG_ADJ_REMAP", 2);
     // blocks of 4 x-rows of tiles per XCD: y-neighbour tiles then share an

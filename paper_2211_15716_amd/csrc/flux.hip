@@ -322,7 +322,7 @@ static int run_fused_zmarch(const FluxArgs &a, const Box &b, hipStream_t s)
     z.nty = (b.j1 - b.j0 + TH - 1) / TH;
     const int depth = b.k1 - b.k0;
     int zc = env_int_flux("IGG_FLUX_ZCHUNK", 0);
-    if (zc < 1) zc = auto_zchunk((int64_t)z.ntx * z.nty, depth, 16);
+    if (zc < 1) zc = zchunk_for_groups((int64_t)z.ntx * z.nty, depth, 16);
     z.zc = zc;
     z.remap = env_int_flux("IGG_FLUX_REMAP", 2);
     const int64_t blocks = (int64_t)z.ntx * z.nty * ((depth + zc - 1) / zc);

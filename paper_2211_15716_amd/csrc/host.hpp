@@ -37,12 +37,14 @@ constexpr int64_t kZmarchMinPoints = (int64_t)1 << 21;
 int64_t zmarch_min_points();
 
 // Planes per z-march work-group: the largest of zc_max, zc_max/2, ... (at
-// least 4) that still gives about 2048 work-groups for `columns` tiles over
-// `depth` planes, so mid-sized grids fill the 256 compute units.
-inline int auto_zchunk(int64_t columns, int depth, int zc_max)
+// least 4) that still gives `target` work-groups for `columns` tiles over
+// `depth` planes.  More, shorter marches balance the compute units better;
+// the planes two chunks share are read at about the same time, mostly from
+// cache, so short chunks add little traffic.
+inline int zchunk_for_groups(int64_t columns, int depth, int zc_max, int64_t target = 2048)
 {
     int zc = zc_max;
-    while (zc > 4 && columns * ((depth + zc - 1) / zc) < 2048) zc /= 2;
+    while (zc > 4 && columns * ((depth + zc - 1) / zc) < target) zc /= 2;
     return zc < 1 ? 1 : zc;
 }
 

@@ -344,7 +344,7 @@ int launch_step_boxes(int dtype, const StepArgs &a, const Box *b, int nb, hipStr
 // work-group.  Chunks of 16 planes gave the best HBM throughput on MI355X
 // at 512^3 (many short marches balance the 256 CUs; the two extra planes
 // per chunk are mostly served from cache); smaller grids halve the chunk
-// (down to 4) to keep about 2048 work-groups.  Keeping each x-row of tiles
+// (down to 4) while the launch would have fewer than min_groups work-groups.  Keeping each x-row of tiles
 // on one XCD cut the inner kernel's L2 fetches by 10% and its time by 6%.
 // Launch settings of one z-march launch: planes per work-group and the
 // work-group to XCD mapping, each with an environment override for tuning.
@@ -353,13 +353,17 @@ struct ZLaunch {
     const char *zc_env;
     int remap;
     const char *remap_env;
+    int64_t min_groups;
 };
-// inner region: 16 planes, x-rows of tiles dealt to the XCDs in turn
-static const ZLaunch kInner = {16, "IGG_ZCHUNK", 2, "IGG_XCD_REMAP"};
+// FP64 inner region (and FP32 rows without vector loads): 16 planes, x-rows
+// of tiles dealt to the XCDs in turn;
+// chunks halved below 4096 work-groups (in a ping-pong time loop 4 planes
+// beat 16 by 5% at 256^3 and by 6% at 384^3, while 16 stay at 512^3)
+static const ZLaunch kInner = {16, "IGG_ZCHUNK", 2, "IGG_XCD_REMAP", 4096};
 // FP32 and FP16 inner region: 16 planes, contiguous ranges of tile rows per XCD
-static const ZLaunch kInnerRanges = {16, "IGG_ZCHUNK", 3, "IGG_XCD_REMAP"};
+static const ZLaunch kInnerRanges = {16, "IGG_ZCHUNK", 3, "IGG_XCD_REMAP", 2048};
 // x slabs: 8 planes, contiguous ranges of tile rows per XCD
-static const ZLaunch kXSlab = {8, "IGG_XSLAB_ZCHUNK", 3, "IGG_XSLAB_REMAP"};
+static const ZLaunch kXSlab = {8, "IGG_XSLAB_ZCHUNK", 3, "IGG_XSLAB_REMAP", 2048};
 
 template <typename S, int VEC, int BX, int TY, int RY, int WRAP = 0>
 static int run_zmarch(const StepArgs &a, const Box *b, int nbox, hipStream_t s, const ZLaunch &L,
@@ -381,7 +385,7 @@ static int run_zmarch(const StepArgs &a, const Box *b, int nbox, hipStream_t s, 
         depth_max = std::max(depth_max, b[q].k1 - b[q].k0);
     }
     int zc = env_int(L.zc_env, 0);
-    if (zc < 1) zc = auto_zchunk(columns, depth_max, L.zc);
+    if (zc < 1) zc = zchunk_for_groups(columns, depth_max, L.zc, L.min_groups);
     z.zc = zc;
     z.remap = env_int(L.remap_env, L.remap);
     z.rblock = std::max(1, env_int("IGG_XCD_BLOCK", 1));
