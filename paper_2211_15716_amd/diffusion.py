@@ -156,6 +156,20 @@ def _zeros_like(x):
     return _map(torch.zeros_like, x)
 
 
+def _fresh_like(x):
+    """New buffers like x holding only x's six halo faces: enough for a step's
+    output, since a step writes every inner point (and the halo planes of
+    periodic dimensions), and the halo planes of non-periodic dimensions are
+    the same in every state."""
+    def one(t):
+        y = torch.empty_like(t)
+        y[0], y[-1] = t[0], t[-1]
+        y[:, 0], y[:, -1] = t[:, 0], t[:, -1]
+        y[:, :, 0], y[:, :, -1] = t[:, :, 0], t[:, :, -1]
+        return y
+    return _map(one, x)
+
+
 def _copy_(dst, src):
     if isinstance(dst, (list, tuple)):
         for d, s_ in zip(dst, src):
@@ -222,7 +236,7 @@ class Sweep:
                     dst = self.pool.pop(q)
                     break
             if dst is None:
-                dst = _clone(self.cur)
+                dst = _fresh_like(self.cur)
             self.p.step(dst, self.cur, self.Ci)
             self.advances += 1
             self.cur, self.cur_n = dst, b
@@ -242,10 +256,11 @@ class Sweep:
         """The forward sweep; returns T_nt (a new tensor)."""
         for op in self.fwd:
             self._do(op)
-        out = _clone(self.cur)  # a copy keeps the non-periodic halo planes
-        if nt > 0:
-            self.p.step(out, self.cur, self.Ci)
-            self.advances += 1
+        if nt == 0:
+            return _clone(self.cur)
+        out = _fresh_like(self.cur)  # carries the non-periodic halo planes
+        self.p.step(out, self.cur, self.Ci)
+        self.advances += 1
         return out
 
     def reverse(self, lam_nt):

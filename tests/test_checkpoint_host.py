@@ -147,7 +147,7 @@ class _RecordingProblem:
 
 @pytest.mark.parametrize("sched", [("store_all",), ("periodic", 3), ("periodic", 16), ("sqrt",), ("binomial", 1),
                                    ("binomial", 2), ("binomial", 4)])
-@pytest.mark.parametrize("nt", [1, 2, 7, 20])
+@pytest.mark.parametrize("nt", [0, 1, 2, 7, 20])
 def test_sweep_executes_schedule_on_buffers(sched, nt):
     """The GPU driver's executor (Sweep, with snapshots written in place
     and freed buffers reused) run on CPU tensors: the forward result is the
@@ -168,26 +168,28 @@ def test_sweep_executes_schedule_on_buffers(sched, nt):
     prob = _RecordingProblem(T0)
     ops = ck.make(sched[0], nt, sched[1] if len(sched) > 1 else None)
     made = []
-    real_clone = diffusion._clone
+    real_clone, real_fresh = diffusion._clone, diffusion._fresh_like
 
-    def counting_clone(x):
-        y = real_clone(x)
-        made.append(y)
-        return y
+    def counting(f):
+        def g(x):
+            y = f(x)
+            made.append(y)
+            return y
+        return g
 
-    diffusion._clone = counting_clone
+    diffusion._clone, diffusion._fresh_like = counting(real_clone), counting(real_fresh)
     try:
         sw = diffusion.Sweep(prob, Ci, T0, ops)
         out = sw.forward(nt)
         assert torch.equal(out, states[nt])
         sw.reverse(torch.zeros_like(T0))
     finally:
-        diffusion._clone = real_clone
+        diffusion._clone, diffusion._fresh_like = real_clone, real_fresh
     assert torch.equal(T0, T0_copy)
     assert len(prob.seen) == nt
     for q, seen in enumerate(prob.seen):
         assert torch.equal(seen, states[nt - 1 - q]), q
-    assert sw.advances == sum(op[2] - op[1] for op in ops if op[0] == "advance") + 1
+    assert sw.advances == sum(op[2] - op[1] for op in ops if op[0] == "advance") + (nt > 0)
     # two work buffers, the forward result, and at most peak-1 snapshot buffers
     assert len(made) <= 3 + sw.peak - 1
 
