@@ -341,10 +341,10 @@ int launch_step_boxes(int dtype, const StepArgs &a, const Box *b, int nb, hipStr
 }
 
 // Tile one or two boxes with TW x TH tiles and march zc planes per
-// work-group.  Chunks of 16 planes gave the best HBM throughput on MI355X
-// at 512^3 (many short marches balance the 256 CUs; the two extra planes
-// per chunk are mostly served from cache); smaller grids halve the chunk
-// (down to 4) while the launch would have fewer than min_groups work-groups.  Keeping each x-row of tiles
+// work-group.  Many short marches balance the 256 CUs, and the two extra
+// planes a chunk reads are mostly served from cache: the chunk (at most 16
+// planes) is halved, down to 4, while the launch would have fewer than
+// min_groups work-groups.  Keeping each x-row of tiles
 // on one XCD cut the inner kernel's L2 fetches by 10% and its time by 6%.
 // Launch settings of one z-march launch: planes per work-group and the
 // work-group to XCD mapping, each with an environment override for tuning.
@@ -356,9 +356,10 @@ struct ZLaunch {
     int64_t min_groups;
 };
 // FP64 inner region (and FP32 rows without vector loads): 16 planes, x-rows
-// of tiles dealt to the XCDs in turn;
-// chunks halved below 4096 work-groups (in a ping-pong time loop 4 planes
-// beat 16 by 5% at 256^3 and by 6% at 384^3, while 16 stay at 512^3)
+// of tiles dealt to the XCDs in turn; chunks halved below 4096 work-groups
+// (in a ping-pong time loop 4 planes beat 16 by 5% at 256^3 and by 6% at
+// 384^3).  At 512^3 8 planes make the unsplit kernel 2% faster but the
+// boundary-first step only 0.3%, so 16 keep the cost of the split low.
 static const ZLaunch kInner = {16, "IGG_ZCHUNK", 2, "IGG_XCD_REMAP", 4096};
 // FP32 and FP16 inner region: 16 planes, contiguous ranges of tile rows per XCD
 static const ZLaunch kInnerRanges = {16, "IGG_ZCHUNK", 3, "IGG_XCD_REMAP", 2048};
