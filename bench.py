@@ -63,6 +63,8 @@ def parse():
                    help="extra timings of --steps steps for the median and its 95%% interval")
     p.add_argument("--profile", action="store_true",
                    help="headline loop only, for running under rocprofv3")
+    p.add_argument("--profile-adjoint", type=int, default=0, metavar="N",
+                   help="for rocprofv3 only: a 1 GiB reference copy, then 6 unsplit FP64 adjoint steps at N^3")
     p.add_argument("--split", default="16,2,2",
                    help="boundary widths of the timed steps, or 'none' for the unsplit schedule")
     return p.parse_args()
@@ -209,6 +211,29 @@ def step_samples(igg, torch, T, C, lam, dt, dx, dy, dz, steps, split, n):
             "min": round(vals[0], 5), "max": round(vals[-1], 5)}
 
 
+def profile_adjoint(igg, torch, synth, n):
+    """The adjoint kernel alone, for HBM byte counters: a plain 1 GiB device
+    copy (the reference that scales the counters), then 6 unsplit FP64
+    adjoint steps on n^3 fields (uniform random lam', T_n, Ci; gCi from 0)."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    igg.init_global_grid(n, n, n, dims=(1, 1, 1), periods=(1, 1, 1), overlaps=(2, 2, 2))
+    lp, Tn, Ci = (torch.from_numpy(a).cuda() for a in synth.uniform_fields(n, n, n, seed=3, lo=0.5, hi=1.5, n=3))
+    igg.update_halo(lp, Tn, Ci)
+    ln, gCi = torch.zeros_like(lp), torch.zeros_like(lp)
+    dx = 1.0 / (n - 1)
+    dt = dx * dx / 1.5 / 6.1
+    for _ in range(6):
+        igg.diffusion_step_adjoint(ln, lp, Tn, Ci, gCi, 1.0, dt, dx, dx, dx, split=None)
+        ln, lp = lp, ln
+    torch.cuda.synchronize()
+    igg.finalize_global_grid()
+    print(json.dumps({"profile_adjoint": n, "points_per_launch": (n - 2) ** 3, "bytes_per_point": 48}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -222,6 +247,9 @@ def main():
     from paper_2211_15716_amd import igg, synth
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
+    if args.profile_adjoint:
+        profile_adjoint(igg, torch, synth, args.profile_adjoint)
+        return
     torch.cuda.set_device(0)
     n = args.n
     K, Wm = args.steps, args.warmup
