@@ -38,7 +38,8 @@
  *     IGG_ZMARCH_MIN_POINTS (smallest region for the z-march kernels).
  *     Read at each launch (tuning): IGG_ZCHUNK, IGG_XCD_REMAP,
  *     IGG_XCD_BLOCK, IGG_XSLAB_ZCHUNK, IGG_XSLAB_REMAP, IGG_ADJ_ZCHUNK,
- *     IGG_ADJ_REMAP, IGG_ADJ_XCD_BLOCK, IGG_FLUX_ZCHUNK, IGG_FLUX_REMAP.
+ *     IGG_ADJ_REMAP, IGG_ADJ_XCD_BLOCK, IGG_ADJ_WAVES, IGG_FLUX_ZCHUNK,
+ *     IGG_FLUX_REMAP.
  */
 #ifndef IGG_MI355X_H
 #define IGG_MI355X_H
