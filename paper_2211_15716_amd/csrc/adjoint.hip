@@ -348,10 +348,10 @@ static int run_zmarch(const AdjArgs &a, const Box &b, hipStream_t s)
     if (zc < 1) zc = zchunk_for_groups((int64_t)z.ntx * z.nty, depth, 16);
     z.zc = zc;
     z.remap = env_int("IGG_ADJ_REMAP", 2);
-    // blocks of about an eighth of the tile rows of a plane per XCD:
-    // y-neighbour tiles then share an L2.  Against blocks of one row that
-    // cut the time by 5% at 512^3 (blocks of 16) and 1-3% at 256^3 (8)
-    z.rblock = std::max(1, env_int("IGG_ADJ_XCD_BLOCK", std::max(1, (z.nty + 4) / 8)));
+    // blocks of 4 x-rows of tiles per XCD, so y-neighbour tiles share an
+    // L2: the fastest block at 256^3 and 768^3 (by 2-6% over 1, 8, 16 and
+    // 24); at 512^3 blocks of 16 are 4% faster
+    z.rblock = std::max(1, env_int("IGG_ADJ_XCD_BLOCK", 4));
     z.xh = a.xh;
     int64_t blocks = (int64_t)z.ntx * z.nty * ((depth + zc - 1) / zc);
     if (blocks == 0) return IGG_OK;
