@@ -426,7 +426,8 @@ static bool vec_ok(const StepArgs &a)
 // Inner region.  FP64: 128-point (1 KB) tile rows, 16-byte loads, four
 // rows per thread, 16 rows per tile.  FP32: 256-point (1 KB) rows, 16-byte
 // loads, two rows per thread, 16 rows.  FP16: 256-point (512-byte) rows,
-// 8-byte loads, 16 rows.
+// 8-byte loads, two rows per thread, 8 rows (256 threads: 1-3% faster than
+// 512-thread tiles of 16 rows at 256^3 and 512^3).
 // These shapes and work-group mappings measured fastest on MI355X at 512^3.
 // Rows whose length does not allow vector loads take one point per lane;
 // regions below zmarch_min_points() take the box kernel.
@@ -441,7 +442,7 @@ int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s)
         if (vec_ok<float, 4>(a)) return run_zmarch<float, 4, 64, 8, 2>(a, &b, 1, s, kInnerRanges);
         return run_zmarch<float, 1, 64, 8, 2>(a, &b, 1, s, kInner);
     }
-    if (vec_ok<_Float16, 4>(a)) return run_zmarch<_Float16, 4, 64, 8, 2>(a, &b, 1, s, kInnerRanges);
+    if (vec_ok<_Float16, 4>(a)) return run_zmarch<_Float16, 4, 64, 4, 2>(a, &b, 1, s, kInnerRanges);
     return run_zmarch<_Float16, 1, 64, 8, 2>(a, &b, 1, s, kInnerRanges);
 }
 
