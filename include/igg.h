@@ -257,7 +257,10 @@ int diffusion_dt(const igg_field *Ci, double lam, double dx, double dy, double d
  * lam_np1 lives on the unique points: its halo is their periodic image in
  * periodic dimensions and zero in non-periodic ones (lam_n's halo planes in
  * non-periodic dimensions are not written, so start lam_n zeroed there).
- * FP64 or FP32 (IGG_ERR_DTYPE for FP16).  `split` as in diffusion_step.
+ * FP64 or FP32 (IGG_ERR_DTYPE for FP16).  `split` as in diffusion_step,
+ * except that by default the slabs, the update and the inner region run as
+ * one chain on `stream` at every size (the adjoint kernel is partly
+ * latency-bound and runs slower with the slabs beside it).
  * Errors: as diffusion_step; IGG_ERR_ALIAS if lam_n or gCi overlaps an input
  * or each other. */
 int diffusion_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1,
@@ -313,7 +316,8 @@ int diffusion_flux_step_ranks(const igg_field *T2, const igg_field *T, const igg
  *   lam_n = lam_np1 - dt*div(p)              (inner cells), then halo(lam_n)
  *   gCi  += -dt*lam_np1.*div(q_n)            (inner cells; halo untouched)
  * T_n is the state the forward step read (valid halo); Ci needs a valid
- * halo.  FP64 or FP32.  `split` as in diffusion_step (widths >= overlap).
+ * halo.  FP64 or FP32.  `split` as in diffusion_step_adjoint (widths >=
+ * overlap).
  * Errors: as diffusion_step_adjoint. */
 int diffusion_flux_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1, const igg_field *T_n,
                                 const igg_field *Ci, const igg_field *gCi, double lam, double dt, double dx,

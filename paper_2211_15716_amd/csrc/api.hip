@@ -272,14 +272,17 @@ static int check_spacings(double lam, double dt, double dx, double dy, double dz
 // a captured graph of a single chain replays fastest, so they take schedule
 // 2.  FP16 fields take schedule 2 at any size: their kernels are partly
 // bound by the vector ALU (stochastic rounding), and slabs running beside
-// the inner region made the 512^3 step 7% slower than the serial chain.  When the x exchange is fused into the stores (or x is not periodic)
+// the inner region made the 512^3 step 7% slower than the serial chain.
+// Callers whose inner kernel is partly latency-bound (the adjoint) pass
+// side_ok = false and take schedule 2 too: its slabs beside the inner
+// region cost 5.5% at 256^3 and 2% at 512^3.  When the x exchange is fused into the stores (or x is not periodic)
 // the update never reads the x slabs, so they join the inner launch and the
 // boundary phase is the y and z slabs.
 // boundary(r, slabs, stream) and inner(r, box, stream) launch rank r's
 // kernels; out holds the nout updated fields of every rank, rank-major.
 template <typename BoundaryLaunch, typename InnerLaunch>
 static int run_split(const int *split, const igg_field *out, int nout, int halo_dims, BoundaryLaunch boundary,
-                     InnerLaunch inner_launch, hipStream_t s)
+                     InnerLaunch inner_launch, hipStream_t s, bool side_ok = true)
 {
     Grid &g = grid();
     int rc;
@@ -297,7 +300,7 @@ static int run_split(const int *split, const igg_field *out, int nout, int halo_
         inner.i0 = 1;
         inner.i1 = g.n[0] - 1;
     }
-    const bool side_pays = box_points(inner) >= kSideMinPoints && out[0].dtype != IGG_F16;
+    const bool side_pays = side_ok && box_points(inner) >= kSideMinPoints && out[0].dtype != IGG_F16;
     const int sched = g.schedule >= 0 ? g.schedule : (side_pays ? 1 : 2);
     const bool on_side = sched == 1, serial = sched == 2;
     hipStream_t bs = on_side ? g.side : s;
@@ -518,7 +521,7 @@ static int adjoint_step(int form, const igg_field *lam_n, const igg_field *lam_n
     return run_split(
         split, lam_n, 1, halo_dims,
         [&](int r, const Split &b, hipStream_t st) { return launch_adjoint_boxes(dt_, args[r], b.boundary, b.nb, st); },
-        [&](int r, const Box &b, hipStream_t st) { return launch_adjoint_inner(dt_, args[r], b, st); }, s);
+        [&](int r, const Box &b, hipStream_t st) { return launch_adjoint_inner(dt_, args[r], b, st); }, s, false);
 }
 
 static int check_face(const igg_field *q, const char *name, int dim)
