@@ -196,8 +196,8 @@ int igg_finalize_global_grid(void);
  *          the helper.  The x exchange is stored by the step kernels as they
  *          compute the points it moves, so the x slabs are computed with the
  *          inner region.  Inner regions below 2^21 points, and FP16 fields
- *          (whose kernels are partly ALU-bound), run slabs, update and inner
- *          region as one chain on `stream`.
+ *          (measured faster that way), run slabs, update and inner region as
+ *          one chain on `stream`.
  *          NULL = no overlap: everything runs on `stream` in order.
  *   rnd    FP16 store rounding, NULL = round to nearest even (ignored for
  *          FP64/FP32).

@@ -270,14 +270,14 @@ static int check_spacings(double lam, double dt, double dx, double dy, double dz
 // large inner regions take schedule 1; small grids are launch-bound, the
 // cross-stream fork and join cost more than the update they would hide, and
 // a captured graph of a single chain replays fastest, so they take schedule
-// 2.  FP16 fields take schedule 2 at any size: their kernels are partly
-// bound by the vector ALU (stochastic rounding), and slabs running beside
-// the inner region made the 512^3 step 7% slower than the serial chain.
+// 2.  FP16 fields take schedule 2 at any size: slabs running beside the
+// inner region made the 512^3 FP16 step 7% slower than the serial chain.
 // Callers whose inner kernel is partly latency-bound (the adjoint) pass
 // side_ok = false and take schedule 2 too: its slabs beside the inner
-// region cost 5.5% at 256^3 and 2% at 512^3.  When the x exchange is fused into the stores (or x is not periodic)
-// the update never reads the x slabs, so they join the inner launch and the
-// boundary phase is the y and z slabs.
+// region cost 5.5% at 256^3 and 2% at 512^3.  When the x exchange is fused
+// into the stores (or x is not periodic) the update never reads the x
+// slabs, so they join the inner launch and the boundary phase is the y and
+// z slabs.
 // boundary(r, slabs, stream) and inner(r, box, stream) launch rank r's
 // kernels; out holds the nout updated fields of every rank, rank-major.
 template <typename BoundaryLaunch, typename InnerLaunch>
