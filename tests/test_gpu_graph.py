@@ -1,4 +1,5 @@
-"""HIP-graph capture of the step chain: replays give the eager bits."""
+"""HIP-graph capture of the step chain (replays give the eager bits) and the
+library's kernel timing events."""
 import numpy as np
 import pytest
 
@@ -85,3 +86,44 @@ def test_native_graph_run_matches_eager(n, split, dt_name):
             out = igg.diffusion_run(T, T.clone(), C, 1.0, dt, dx, dx, dx, 5, split=split,
                                     rnd=igg.rounding("stochastic", 9, 0), graph=False)
             assert np.array_equal(host(out), sr)
+
+
+@pytest.mark.parametrize("split", [(4, 3, 3), None])
+def test_kernel_timing_events_count_launches_and_points(split):
+    """The library's kernel timing (the figures the benchmark's roofline
+    takes): with timing on, each step adds one inner launch of the expected
+    number of points and a positive duration; a read resets the totals;
+    more launches than the pre-made event pool grow it; with timing off
+    nothing is counted; and timing does not change a result bit."""
+    n = (40, 36, 34)
+    nx, ny, nz = n
+    rng = np.random.default_rng(71)
+    T0 = rng.uniform(1.0, 2.0, (nz, ny, nx))
+    Ci = rng.uniform(0.5, 1.5, (nz, ny, nx))
+    oracle.halo(T0)
+    oracle.halo(Ci)
+    dx = 1.0 / (nx - 1)
+    dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
+    if split is None:
+        pts = (nx - 2) * (ny - 2) * (nz - 2)
+    else:  # x slabs join the inner launch; y and z slabs are the boundary
+        pts = (nx - 2) * (ny - 2 * split[1]) * (nz - 2 * split[2])
+    with grid(n):
+        say("timing", split)
+        T, C = dev(T0), dev(Ci)
+        ref = diffusion.forward(T.clone(), C, 6, 1.0, dt, dx, dx, dx, split=split)
+        igg.timing_enable(True)
+        out = diffusion.forward(T.clone(), C, 6, 1.0, dt, dx, dx, dx, split=split)
+        ms, launches, points, bms = igg.timing_read()
+        assert torch.equal(out, ref)
+        assert launches == 6 and points == 6 * pts
+        assert ms > 0.0
+        assert (bms > 0.0) == (split is not None)
+        assert igg.timing_read() == (0.0, 0, 0, 0.0)
+        # more timed launches than the 2048 events made up front
+        diffusion.forward(T.clone(), C, 1100, 1.0, dt, dx, dx, dx, split=split)
+        ms, launches, points, bms = igg.timing_read()
+        assert launches == 1100 and points == 1100 * pts and ms > 0.0
+        igg.timing_enable(False)
+        diffusion.forward(T.clone(), C, 3, 1.0, dt, dx, dx, dx, split=split)
+        assert igg.timing_read() == (0.0, 0, 0, 0.0)
