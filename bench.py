@@ -70,18 +70,24 @@ def parse():
     return p.parse_args()
 
 
-def kernel_source_hash():
-    """Hash of the code (comments and layout dropped) of the sources the
-    inner step kernel is built from, so an edit of a comment keeps the
-    counters taken on that kernel valid."""
+def code_hash(sources):
+    """Hash of C++ source texts with comments and layout dropped."""
     h = hashlib.sha256()
-    for f in ("step.hip", "device.hpp"):
-        with open(os.path.join(ROOT, "paper_2211_15716_amd", "csrc", f)) as fh:
-            src = fh.read()
+    for src in sources:
         src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
         src = re.sub(r"//[^\n]*", " ", src)
         h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
+
+
+def kernel_source_hash():
+    """Hash of the code of the sources the inner step kernel is built from,
+    so an edit of a comment keeps the counters taken on that kernel valid."""
+    texts = []
+    for f in ("step.hip", "device.hpp"):
+        with open(os.path.join(ROOT, "paper_2211_15716_amd", "csrc", f)) as fh:
+            texts.append(fh.read())
+    return code_hash(texts)
 
 
 def traffic_from_profiles(kernel_hash, key):
