@@ -36,7 +36,8 @@
  *     type), IGG_X_EXCHANGE ("halo": x slabs and an x pass of the halo
  *     update instead of the x exchange stored by the step kernels),
  *     IGG_ZMARCH_MIN_POINTS (smallest region for the z-march kernels).
- *     Read at each launch (tuning): IGG_ZCHUNK, IGG_XCD_REMAP,
+ *     Read at each launch (tuning): IGG_FP64_MIDTILE_MAX_POINTS (regions
+ *     below it take the 512-thread FP64 step tile), IGG_ZCHUNK, IGG_XCD_REMAP,
  *     IGG_XCD_BLOCK, IGG_XSLAB_ZCHUNK, IGG_XSLAB_REMAP, IGG_ADJ_ZCHUNK,
  *     IGG_ADJ_REMAP, IGG_ADJ_XCD_BLOCK, IGG_ADJ_WAVES, IGG_FLUX_ZCHUNK,
  *     IGG_FLUX_REMAP.

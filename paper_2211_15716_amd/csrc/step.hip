@@ -427,7 +427,7 @@ static bool vec_ok(const StepArgs &a)
 }
 
 // Inner region.  FP64: 128-point (1 KB) tile rows, 16-byte loads, four
-// rows per thread, 16 rows per tile.  FP32: 256-point (1 KB) rows, 16-byte
+// rows per thread, 16 rows per tile (two rows per thread below 2^26 points).  FP32: 256-point (1 KB) rows, 16-byte
 // loads, two rows per thread, 16 rows.  FP16: 256-point (512-byte) rows,
 // 8-byte loads, two rows per thread, 8 rows (256 threads: 1-3% faster than
 // 512-thread tiles of 16 rows at 256^3 and 512^3).
@@ -438,7 +438,16 @@ int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s)
 {
     if (box_count(b) < zmarch_min_points()) return launch_step_boxes(dtype, a, &b, 1, s);
     if (dtype == IGG_F64) {
-        if (vec_ok<double, 2>(a)) return run_zmarch<double, 2, 64, 4, 4>(a, &b, 1, s, kInner);
+        if (vec_ok<double, 2>(a)) {
+            // the same 128 x 16 tile over 512 threads of 2 rows (108 registers,
+            // 4 waves per SIMD): 2-3% faster at 256^3 and 384^3, 5% slower at
+            // 512^3, so regions below 2^26 points take it
+            static const char *kMidEnv = "IGG_FP64_MIDTILE_MAX_POINTS";
+            const char *e = getenv(kMidEnv);
+            const int64_t mid_max = (e && *e) ? atoll(e) : ((int64_t)1 << 26);
+            if (box_count(b) < mid_max) return run_zmarch<double, 2, 64, 8, 2>(a, &b, 1, s, kInner);
+            return run_zmarch<double, 2, 64, 4, 4>(a, &b, 1, s, kInner);
+        }
         return run_zmarch<double, 1, 64, 8, 2>(a, &b, 1, s, kInner);
     }
     if (dtype == IGG_F32) {

@@ -90,9 +90,13 @@ def test_c1_forward_matches_oracle(split):
 
 
 @pytest.mark.parametrize("n", [(67, 45, 38), (130, 70, 40), (33, 9, 11), (64, 64, 64)])
-def test_forward_ragged_sizes(n):
-    """Sizes spanning several tiles with ragged tails, odd nx (scalar path)."""
-    say("forward ragged", n)
+@pytest.mark.parametrize("mid", [None, "0"])
+def test_forward_ragged_sizes(n, mid, monkeypatch):
+    """Sizes spanning several tiles with ragged tails, odd nx (scalar path);
+    FP64 tiles of both shapes (mid = "0" forces the large-region one)."""
+    if mid is not None:
+        monkeypatch.setenv("IGG_FP64_MIDTILE_MAX_POINTS", mid)
+    say("forward ragged", n, mid)
     nx, ny, nz = n
     T0, Ci = synth.noisy_state_uniform_ci(nx, ny, nz, seed=5, noise=1e-2)
     oracle.halo(T0)
@@ -220,9 +224,11 @@ def test_schedules_and_x_exchange_forms_bit_exact(dt_name, monkeypatch):
 
 @pytest.mark.parametrize("n", [(32, 32, 32), (96, 52, 41), (130, 70, 40), (33, 9, 11)])
 @pytest.mark.parametrize("dt_name", ["f64", "f32", "f16"])
-def test_box_kernel_and_zmarch_paths_bit_exact(n, dt_name):
+def test_box_kernel_and_zmarch_paths_bit_exact(n, dt_name, monkeypatch):
     """Small regions go to the one-thread-per-point box kernel by default;
-    forced through the z-march kernels they give the same bits."""
+    forced through the z-march kernels (FP64: both tile shapes, the 512-thread
+    one of mid-sized regions and the 256-thread one of large regions) they
+    give the same bits."""
     nx, ny, nz = n
     T0, Ci = synth.noisy_state_uniform_ci(nx, ny, nz, seed=31, noise=1e-2)
     oracle.halo(T0)
@@ -230,7 +236,11 @@ def test_box_kernel_and_zmarch_paths_bit_exact(n, dt_name):
     dx = 1.0 / (nx - 1)
     dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
     outs = []
-    for zmin in (None, 0):
+    for zmin, mid in ((None, None), (0, None), (0, "0")):
+        if mid is None:
+            monkeypatch.delenv("IGG_FP64_MIDTILE_MAX_POINTS", raising=False)
+        else:
+            monkeypatch.setenv("IGG_FP64_MIDTILE_MAX_POINTS", mid)
         with grid(n, zmarch_min=zmin):
             T, C = dev(T0, DT[dt_name]), dev(Ci, DT[dt_name])
             for split in [None, (16, 2, 2)]:
