@@ -143,6 +143,14 @@ def test_step_validation_before_any_hip_call(host_grid):
     I3s = ctypes.c_int * 3
     assert lib.diffusion_flux_step(r(T2), r(T), r(C), *[r(x) for x in qf], 1.0, 1e-3, .1, .1, .1,
                                    I3s(16, 2, 2), None) == igg.IGG_ERR_ARG
+    # flux form and its adjoint: FP16 refused
+    h16 = [_field(0x60000000 + 0x1000000 * d, igg.IGG_F16, n) for d in range(3)]
+    qh = [_field(0x70000000 + 0x1000000 * d, igg.IGG_F16, tuple(m + (e == d) for e, m in enumerate(n)))
+          for d in range(3)]
+    assert lib.diffusion_flux_step(*[r(x) for x in h16], *[r(x) for x in qh], 1.0, 1e-3, .1, .1, .1,
+                                   None, None) == igg.IGG_ERR_DTYPE
+    assert lib.diffusion_flux_step_adjoint(*[r(h) for h in H], 1.0, 1e-3, .1, .1, .1, None,
+                                           None) == igg.IGG_ERR_DTYPE
     # reductions
     out = ctypes.c_double()
     assert lib.igg_reduce(99, r(T), None, r(out), None) == igg.IGG_ERR_ARG
