@@ -358,3 +358,96 @@ def test_light_cone_sampler_matches_full_run():
     pts = [(1, 1, 1), (18, 18, 18), (5, 11, 17), (10, 2, 9)]
     got = oracle.run_points(T0, Ci, nt, 1.0, dt, dx, dx, dx, pts)
     assert np.array_equal(got, np.array([full[k, j, i] for (i, j, k) in pts]))
+
+
+# --------------------------------------------------------------------------- adjoint with non-periodic dimensions
+def _d2_line(N, periodic):
+    """1-D second difference on the N unknowns of a line: with a periodic
+    wrap, or with the line's two outer neighbours fixed boundary values (they
+    only add a constant, so the matrix couples the unknowns alone)."""
+    if periodic:
+        return _periodic_d2(N)
+    D = -2.0 * np.eye(N)
+    D += np.eye(N, k=1) + np.eye(N, k=-1)
+    return D
+
+
+def _affine_operator(T0, periods, spacings):
+    """The step on the inner points of a grid whose non-periodic dimensions
+    keep their boundary planes fixed, as t -> t + a*c.*(L t + b): L is the
+    Kronecker sum of the per-dimension line operators (x fastest) and b the
+    fixed boundary planes' contribution, read straight from T0."""
+    nz, ny, nx = T0.shape
+    Ns = (nx - 2, ny - 2, nz - 2)
+    I = [np.eye(N) for N in Ns]
+    D = [_d2_line(N, p) / d**2 for N, p, d in zip(Ns, periods, spacings)]
+    L = (np.kron(np.kron(I[2], I[1]), D[0]) + np.kron(np.kron(I[2], D[1]), I[0]) +
+         np.kron(np.kron(D[2], I[1]), I[0]))
+    b = np.zeros((nz - 2, ny - 2, nx - 2))
+    dx, dy, dz = spacings
+    if not periods[0]:
+        b[:, :, 0] += T0[1:-1, 1:-1, 0] / dx**2
+        b[:, :, -1] += T0[1:-1, 1:-1, -1] / dx**2
+    if not periods[1]:
+        b[:, 0, :] += T0[1:-1, 0, 1:-1] / dy**2
+        b[:, -1, :] += T0[1:-1, -1, 1:-1] / dy**2
+    if not periods[2]:
+        b[0, :, :] += T0[0, 1:-1, 1:-1] / dz**2
+        b[-1, :, :] += T0[-1, 1:-1, 1:-1] / dz**2
+    return L, b.ravel()
+
+
+@pytest.mark.parametrize("periods", [(1, 0, 1), (0, 0, 0), (0, 1, 1)])
+def test_gradient_with_fixed_boundary_planes_equals_dense_formulation(periods):
+    """In a non-periodic dimension the boundary planes are fixed inputs: the
+    unknowns are the inner points, each step is the affine map
+    t -> t + a*c.*(L t + b), the loss 0.5*|t_nt - t_obs|^2 over them.  Its
+    gradients follow from dense matrices with no adjoint code involved:
+      dL/dT0 = (M^nt)^T r,  M = I + a*diag(c)*L,  r = t_nt - t_obs,
+      dL/dCi = sum_n a*lam_{n+1} .* (L t_n + b),  lam_{n+1} = (M^T)^(nt-1-n) r.
+    The oracle's forward run, loss and both gradients must agree (so lambda
+    carries nothing into the boundary planes), and central differences
+    confirm the Ci gradient at points next to a fixed boundary."""
+    nx, ny, nz = 7, 6, 8
+    spacings = (0.19, 0.23, 0.16)
+    T0, Ci, Tobs = synth.uniform_fields(nx, ny, nz, seed=41, lo=0.3, hi=1.0, n=3)
+    for A in (T0, Ci, Tobs):
+        oracle.halo(A, (2, 2, 2), periods)
+    lam, nt = 0.8, 7
+    dt = oracle.time_step(*spacings, lam, oracle.max_all(Ci))
+    a = dt * lam
+    L, b = _affine_operator(T0, periods, spacings)
+    c = _inner(Ci).ravel()
+    M = np.eye(L.shape[0]) + a * np.diag(c) @ L
+    ts = [_inner(T0).ravel().copy()]
+    for _ in range(nt):
+        t = ts[-1]
+        ts.append(t + a * c * (L @ t + b))
+    T_nt = oracle.run(T0, Ci, nt, lam, dt, *spacings, periods=periods)
+    assert np.max(np.abs(_inner(T_nt).ravel() - ts[-1])) <= 1e-13 * np.max(np.abs(ts[-1]))
+    r = ts[-1] - _inner(Tobs).ravel()
+    gT_expect = np.linalg.matrix_power(M, nt).T @ r
+    gC_expect = np.zeros_like(c)
+    lam_v = r.copy()
+    for n in range(nt - 1, -1, -1):
+        gC_expect += a * lam_v * (L @ ts[n] + b)
+        lam_v = M.T @ lam_v
+    Lval, gT0, gCi = oracle.gradient(T0, Ci, Tobs, nt, lam, dt, *spacings, periods=periods)
+    assert abs(Lval - 0.5 * float(r @ r)) <= 1e-13 * Lval
+    assert np.max(np.abs(_inner(gT0).ravel() - gT_expect)) <= 1e-12 * np.max(np.abs(gT_expect))
+    assert np.max(np.abs(_inner(gCi).ravel() - gC_expect)) <= 1e-12 * np.max(np.abs(gC_expect))
+    # boundary planes carry no gradient
+    for G in (gT0, gCi):
+        assert np.all(G[0] == 0) and np.all(G[-1] == 0) and np.all(G[:, 0] == 0) and np.all(G[:, :, -1] == 0)
+    # central differences in Ci next to the fixed boundary (and inside)
+    g = _inner(gCi)
+    for (k, j, i) in [(1, 1, 1), (nz - 2, ny - 2, nx - 2), (3, 1, 5), (1, 4, 3)]:
+        h = 1e-4 * Ci[k, j, i]
+        vals = []
+        for s in (+1, -1):
+            C2 = Ci.copy()
+            C2[k, j, i] += s * h
+            oracle.halo(C2, (2, 2, 2), periods)
+            vals.append(oracle.loss(oracle.run(T0, C2, nt, lam, dt, *spacings, periods=periods), Tobs))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g[k - 1, j - 1, i - 1]) <= 1e-6 * max(abs(fd), 1e-3 * np.max(np.abs(g)))
