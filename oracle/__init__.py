@@ -214,31 +214,37 @@ def gradient(T0, Ci, T_obs, nt, lam, dt, dx, dy, dz, every=1, ol=(2, 2, 2), peri
     The forward states are recomputed from snapshots taken every `every`
     steps (every=1 keeps all states).  dt is held fixed, not recomputed from
     Ci.  Returns (loss, dL/dT0, dL/dCi) with zero halos in the gradients."""
+    # Buffers are made once and reused (a step writes every inner point and
+    # the halo update every periodic halo plane; the halo planes of
+    # non-periodic dimensions are T0's in every state and zero in lambda),
+    # so large grids do not pay for a fresh array per step.
     snaps = {}
     T = np.array(T0, dtype=np.float64, copy=True)
+    W = T.copy()
     for it in range(nt):
         if it % every == 0:
             snaps[it] = T.copy()
-        T2 = step(T, Ci, lam, dt, dx, dy, dz, out=T.copy())
-        halo(T2, ol, periods)
-        T = T2
+        step(T, Ci, lam, dt, dx, dy, dz, out=W)
+        halo(W, ol, periods)
+        T, W = W, T
     L = loss(T, T_obs)
     lp = np.zeros_like(T)
     inner(lp)[...] = inner(T) - inner(T_obs)
     halo(lp, ol, periods)
+    ln = np.zeros_like(T)
     gCi = np.zeros_like(T)
+    seg = [W] + [T0.copy() for _ in range(min(every, nt) - 2)] if every > 1 else []
     seg_start = ((nt - 1) // every) * every
     while seg_start >= 0:
         seg_end = min(seg_start + every, nt)
         states = [snaps[seg_start]]
-        for _ in range(seg_start, seg_end - 1):
-            T2 = step(states[-1], Ci, lam, dt, dx, dy, dz, out=states[-1].copy())
-            halo(T2, ol, periods)
-            states.append(T2)
+        for q in range(seg_end - seg_start - 1):
+            states.append(step(states[-1], Ci, lam, dt, dx, dy, dz, out=seg[q]))
+            halo(states[-1], ol, periods)
         for it in range(seg_end - 1, seg_start - 1, -1):
-            ln = adjoint_step(lp, states[it - seg_start], Ci, gCi, lam, dt, dx, dy, dz)
+            adjoint_step(lp, states[it - seg_start], Ci, gCi, lam, dt, dx, dy, dz, out=ln)
             halo(ln, ol, periods)
-            lp = ln
+            lp, ln = ln, lp
         seg_start -= every
     gT0 = np.zeros_like(T)
     inner(gT0)[...] = inner(lp)
@@ -291,6 +297,22 @@ def flux_run(T0, Ci, nt, lam, dt, dx, dy, dz, overlaps=(2, 2, 2), periods=(1, 1,
         flux_halo(T2, q, overlaps, periods)
         T = T2
     return (T, q) if return_q else T
+
+
+def flux_run_points(T0, Ci, nt, lam, dt, dx, dy, dz, points):
+    """T_nt of the flux-form time loop at selected inner cells (i, j, k) of a
+    fully periodic grid, by the light-cone argument of run_points: a cell's
+    faces and update read only its six neighbours, so after s steps a cell
+    depends on the cells within s of it, and each sample runs flux_run on the
+    box of radius nt around it with the box boundary held fixed."""
+    out = []
+    zero = (0, 0, 0)
+    for (i, j, k) in points:
+        Tb = _periodic_box(T0, (i, j, k), nt)
+        Cb = _periodic_box(Ci, (i, j, k), nt)
+        Tr = flux_run(Tb, Cb, nt, lam, dt, dx, dy, dz, overlaps=(2, 2, 2), periods=zero)
+        out.append(Tr[nt, nt, nt])
+    return np.array(out)
 
 
 def flux_adjoint_step(lp, Ci, q, gCi, lam, dt, dx, dy, dz, out=None):

@@ -51,6 +51,16 @@ def forward(T, Ci, nt, lam, dt, dx, dy, dz, split=(16, 2, 2), work=None, sr_seed
     return a
 
 
+def forward_with(prob, T, Ci, nt, stream=None):
+    """nt steps of `prob` (a Problem or FluxProblem) from T (valid halo),
+    swapping two buffers as the Fig. 1 loop does; returns the final state."""
+    a, b = T, T.clone()
+    for _ in range(nt):
+        prob.step(b, a, Ci, stream=stream)
+        a, b = b, a
+    return a
+
+
 # --------------------------------------------------------------------------- adjoint sweep
 class Problem:
     """Constants of one time loop: lam, dt (held fixed), spacings, split."""

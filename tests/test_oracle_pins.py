@@ -451,3 +451,15 @@ def test_gradient_with_fixed_boundary_planes_equals_dense_formulation(periods):
             vals.append(oracle.loss(oracle.run(T0, C2, nt, lam, dt, *spacings, periods=periods), Tobs))
         fd = (vals[0] - vals[1]) / (2 * h)
         assert abs(fd - g[k - 1, j - 1, i - 1]) <= 1e-6 * max(abs(fd), 1e-3 * np.max(np.abs(g)))
+
+
+def test_flux_light_cone_sampler_matches_full_run():
+    n, nt = 20, 6
+    T0, Ci = synth.noisy_state_uniform_ci(n, n, n, seed=15, noise=1e-2)
+    T0, Ci = _with_halo(T0), _with_halo(Ci)
+    dx = 1.0 / (n - 1)
+    dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
+    full = oracle.flux_run(T0, Ci, nt, 1.0, dt, dx, dx, dx)
+    pts = [(1, 1, 1), (18, 18, 18), (5, 11, 17), (10, 2, 9)]
+    got = oracle.flux_run_points(T0, Ci, nt, 1.0, dt, dx, dx, dx, pts)
+    assert np.array_equal(got, np.array([full[k, j, i] for (i, j, k) in pts]))
