@@ -234,6 +234,24 @@ static int64_t box_points(const Box &b)
     return (int64_t)std::max(0, b.i1 - b.i0) * std::max(0, b.j1 - b.j0) * std::max(0, b.k1 - b.k0);
 }
 
+// A fixed-length wait on one wavefront, `iters` rounds of the longest
+// s_sleep: put into one stream by the IGG_TEST_DELAY setting, it lets a test
+// hold back one side of the boundary-first schedule and check that the
+// events between the streams, not the timing, order the work.
+__global__ void k_test_delay(int iters)
+{
+    for (int q = 0; q < iters; ++q) __builtin_amdgcn_s_sleep(127);
+}
+
+static int test_delay(int where, hipStream_t s)
+{
+    Grid &g = grid();
+    if (g.delay_where != where || g.delay_iters <= 0) return IGG_OK;
+    hipLaunchKernelGGL(k_test_delay, dim3(1), dim3(64), 0, s, g.delay_iters);
+    IGG_HIP(hipGetLastError());
+    return IGG_OK;
+}
+
 // inner regions of at least this many points run the boundary slabs and the
 // halo update on the helper stream by default, smaller ones in one chain on
 // the caller stream
@@ -279,9 +297,9 @@ static int check_spacings(double lam, double dt, double dx, double dy, double dz
 // slabs, so they join the inner launch and the boundary phase is the y and
 // z slabs.
 // boundary(r, slabs, stream) and inner(r, box, stream) launch rank r's
-// kernels; out holds the nout updated fields of every rank, rank-major.
-template <typename BoundaryLaunch, typename InnerLaunch>
-static int run_split(const int *split, const igg_field *out, int nout, int halo_dims, BoundaryLaunch boundary,
+// kernels, halo(stream) the halo update of the results.
+template <typename HaloLaunch, typename BoundaryLaunch, typename InnerLaunch>
+static int run_split(const int *split, int dtype, HaloLaunch halo, BoundaryLaunch boundary,
                      InnerLaunch inner_launch, hipStream_t s, bool side_ok = true)
 {
     Grid &g = grid();
@@ -300,7 +318,7 @@ static int run_split(const int *split, const igg_field *out, int nout, int halo_
         inner.i0 = 1;
         inner.i1 = g.n[0] - 1;
     }
-    const bool side_pays = side_ok && box_points(inner) >= kSideMinPoints && out[0].dtype != IGG_F16;
+    const bool side_pays = side_ok && box_points(inner) >= kSideMinPoints && dtype != IGG_F16;
     const int sched = g.schedule >= 0 ? g.schedule : (side_pays ? 1 : 2);
     const bool on_side = sched == 1, serial = sched == 2;
     hipStream_t bs = on_side ? g.side : s;
@@ -308,6 +326,7 @@ static int run_split(const int *split, const igg_field *out, int nout, int halo_
         IGG_HIP(hipEventRecord(g.ev_fork, s));
         IGG_HIP(hipStreamWaitEvent(g.side, g.ev_fork, 0));
     }
+    if ((rc = test_delay(1, on_side ? g.side : s))) return rc;
     if (bnd.nb) {
         if ((rc = timing_mark(bs, 1))) return rc;
         for (int r = 0; r < g.nranks; ++r)
@@ -315,15 +334,18 @@ static int run_split(const int *split, const igg_field *out, int nout, int halo_
         if ((rc = timing_mark(bs, 1))) return rc;
     }
     if (serial) {
-        if ((rc = launch_halo(out, nout, s, halo_dims))) return rc;
+        if ((rc = test_delay(3, s))) return rc;
+        if ((rc = halo(s))) return rc;
     } else {
         if (!on_side) {
             IGG_HIP(hipEventRecord(g.ev_fork, s));
             IGG_HIP(hipStreamWaitEvent(g.side, g.ev_fork, 0));
         }
-        if ((rc = launch_halo(out, nout, g.side, halo_dims))) return rc;
+        if ((rc = test_delay(3, g.side))) return rc;
+        if ((rc = halo(g.side))) return rc;
         IGG_HIP(hipEventRecord(g.ev_join, g.side));
     }
+    if ((rc = test_delay(2, s))) return rc;
     for (int r = 0; r < g.nranks && box_points(inner) > 0; ++r) {
         if ((rc = timing_mark(s, 0))) return rc;
         if ((rc = inner_launch(r, inner, s))) return rc;
@@ -354,8 +376,12 @@ static int step_args(int r, const igg_field *T2, const igg_field *T, const igg_f
             (side == 0 ? xh.d_lo : xh.d_hi) = diff / esz;
         }
     }
+    // global indices wrap at the period of a periodic dimension (a point and
+    // its copies in overlapping planes draw the same random bits)
+    int per[3];
+    for (int d = 0; d < 3; ++d) per[d] = g.periods[d] ? g.dims[d] * (g.n[d] - g.ol[d]) : 0;
     const SrOrigin so{c[0] * (g.n[0] - g.ol[0]), c[1] * (g.n[1] - g.ol[1]), c[2] * (g.n[2] - g.ol[2]),
-                      g.dims[0] * (g.n[0] - g.ol[0]) + g.ol[0]};
+                      g.dims[0] * (g.n[0] - g.ol[0]) + g.ol[0], per[0], per[1], per[2]};
     a = StepArgs{T2[r].data, T[r].data, Ci[r].data, g.n[0], g.n[1], g.n[2],
                  dt * lam, 1.0 / (dx * dx), 1.0 / (dy * dy), 1.0 / (dz * dz), key, stochastic, xh, so};
     return IGG_OK;
@@ -416,8 +442,21 @@ static int step_ranks(const igg_field *T2, const igg_field *T, const igg_field *
         }
         return launch_halo(T2, 1, s, halo_dims);
     }
+    // One rank, periodic in every dimension, x exchange in the stores: the
+    // slab kernel packs the y and z planes as it computes them, and the
+    // exchange and unpack are one copy into the halo planes.
+    if (P == 1 && g.fuse_x && g.slab_pack && g.periods[0] && g.periods[1] && g.periods[2]) {
+        SlabPack pk{};
+        for (int d = 0; d < 2; ++d)
+            for (int side = 0; side < 2; ++side) pk.send[d][side] = halo_send_plane(0, d, side);
+        for (int d = 0; d < 3; ++d) pk.ol[d] = g.ol[d];
+        return run_split(
+            split, dtype, [&](hipStream_t st) { return launch_unpack_self(T2[0], pk, st); },
+            [&](int r, const Split &b, hipStream_t st) { return launch_step_slabs(dtype, args[r], b, &pk, st); },
+            [&](int r, const Box &b, hipStream_t st) { return launch_step_inner(dtype, args[r], b, st); }, s);
+    }
     return run_split(
-        split, T2, 1, halo_dims,
+        split, dtype, [&](hipStream_t st) { return launch_halo(T2, 1, st, halo_dims); },
         [&](int r, const Split &b, hipStream_t st) { return launch_step_boundary(dtype, args[r], b, st); },
         [&](int r, const Box &b, hipStream_t st) { return launch_step_inner(dtype, args[r], b, st); }, s);
 }
@@ -519,7 +558,7 @@ static int adjoint_step(int form, const igg_field *lam_n, const igg_field *lam_n
         return launch_halo(lam_n, 1, s, halo_dims);
     }
     return run_split(
-        split, lam_n, 1, halo_dims,
+        split, dt_, [&](hipStream_t st) { return launch_halo(lam_n, 1, st, halo_dims); },
         [&](int r, const Split &b, hipStream_t st) { return launch_adjoint_boxes(dt_, args[r], b.boundary, b.nb, st); },
         [&](int r, const Box &b, hipStream_t st) { return launch_adjoint_inner(dt_, args[r], b, st); }, s, false);
 }
@@ -621,7 +660,7 @@ static int flux_step_ranks(const igg_field *T2, const igg_field *T, const igg_fi
         return launch_halo(hf.data(), 4, s, halo_dims);
     }
     return run_split(
-        split, hf.data(), 4, halo_dims,
+        split, ty, [&](hipStream_t st) { return launch_halo(hf.data(), 4, st, halo_dims); },
         [&](int r, const Split &b, hipStream_t st) { return launch_flux_boxes(ty, args[r], b.boundary, b.nb, st); },
         [&](int r, const Box &b, hipStream_t st) { return launch_flux_inner(ty, args[r], b, st); }, s);
 }
@@ -676,6 +715,27 @@ int igg_init_global_grid(int nx, int ny, int nz, const int dims[3], const int pe
         g.schedule = (sv >= 0 && sv <= 2) ? sv : -1;  // anything else: chosen by size and type
         const char *x = getenv("IGG_X_EXCHANGE");
         g.fuse_x = !(x && strcmp(x, "halo") == 0);
+        // IGG_TEST_DELAY=<where>:<rounds>, where = side (before the helper
+        // stream's first launch), inner (before the inner launch) or halo
+        // (before the halo update); rounds of about 3.4 us each, at most 4096
+        g.delay_where = 0;
+        g.delay_iters = 0;
+        const char *td = getenv("IGG_TEST_DELAY");
+        if (td && *td) {
+            const char *c = strchr(td, ':');
+            const size_t len = c ? (size_t)(c - td) : strlen(td);
+            int where = 0;
+            if (len == 4 && strncmp(td, "side", 4) == 0) where = 1;
+            if (len == 5 && strncmp(td, "inner", 5) == 0) where = 2;
+            if (len == 4 && strncmp(td, "halo", 4) == 0) where = 3;
+            const int it = c ? atoi(c + 1) : 0;
+            if (where && it > 0) {
+                g.delay_where = where;
+                g.delay_iters = std::min(it, 4096);
+            }
+        }
+        const char *sp = getenv("IGG_SLAB_PACK");
+        g.slab_pack = !(sp && strcmp(sp, "0") == 0);
         const char *zm = getenv("IGG_ZMARCH_MIN_POINTS");
         g.zmarch_min = (zm && *zm) ? atoll(zm) : kZmarchMinPoints;
     }

@@ -86,6 +86,32 @@ __device__ __forceinline__ uint32_t point_bits(uint32_t pk, int i, int j, int nx
     return pcg_hash(pk ^ (uint32_t)(i + nx * j));
 }
 
+// Global origin of a block for the FP16 stochastic-rounding hash: the point
+// (i, j, k) of the block is hashed as (i + ox, j + oy, k + oz) in a global
+// index space gnx points wide, so every decomposition rounds a point alike.
+// In a periodic dimension global indices g and g + p* (p* = dims*(n-ol), the
+// period) are one physical point, held by overlapping planes of the same or
+// neighbouring blocks; the index is taken modulo the period (0: not
+// periodic), so every copy of a point draws the same random bits.
+struct SrOrigin {
+    int ox, oy, oz, gnx;
+    int px, py, pz;
+};
+
+__device__ __forceinline__ int sr_wrap(int g, int p) { return (p && g >= p) ? g - p : g; }
+
+// Key of plane k of a block for the key of a (seed, counter) pair.
+__device__ __forceinline__ uint32_t sr_plane_key(uint32_t key, int k, const SrOrigin &so)
+{
+    return plane_key(key, sr_wrap(k + so.oz, so.pz));
+}
+
+// Random word of point (i, j) of a block's plane with key pk.
+__device__ __forceinline__ uint32_t sr_point_bits(uint32_t pk, int i, int j, const SrOrigin &so)
+{
+    return point_bits(pk, sr_wrap(i + so.ox, so.px), sr_wrap(j + so.oy, so.py), so.gnx);
+}
+
 // ---------------------------------------------------- FP16 stores
 // Unbiased stochastic rounding of a float to FP16: x is rounded up to the
 // next FP16 value with probability equal to its distance from the lower one

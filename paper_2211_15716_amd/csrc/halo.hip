@@ -80,6 +80,86 @@ static unsigned char *recv_buf(Grid &g, int r, int f, int side)
     return g.halo_buf + ((size_t)r * 4 * IGG_MAX_FIELDS + 2 * IGG_MAX_FIELDS + f * 2 + side) * g.halo_cap;
 }
 
+unsigned char *halo_send_plane(int r, int f, int side) { return send_buf(grid(), r, f, side); }
+
+// Exchange and unpack of the planes the boundary-slab kernel packed, for a
+// rank that is its own neighbour: the receive side of the exchange is the
+// destination halo plane itself, so each element is copied once, from the
+// send buffer into the field.  d[q] is plane q: element (a, b) of the
+// packed plane (a fastest) goes to dst[a*sa + b*sb], units of esz bytes.
+struct PlaneCopy {
+    const unsigned char *src;
+    unsigned char *dst;
+    int64_t sa, sb;
+    int na, nb;
+    int esz;
+};
+struct PlaneCopySet {
+    PlaneCopy d[4];
+};
+
+template <typename E>
+__device__ __forceinline__ void copy_elem(const PlaneCopy &d, int64_t e)
+{
+    const int a = (int)(e % d.na);
+    const int b = (int)(e / d.na);
+    reinterpret_cast<E *>(d.dst)[(int64_t)a * d.sa + (int64_t)b * d.sb] = reinterpret_cast<const E *>(d.src)[e];
+}
+
+__global__ void __launch_bounds__(256) k_unpack_planes(PlaneCopySet ps)
+{
+    const PlaneCopy &d = ps.d[blockIdx.y];
+    const int64_t count = (int64_t)d.na * d.nb;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        switch (d.esz) {
+        case 16: copy_elem<uint4>(d, e); break;
+        case 8: copy_elem<uint64_t>(d, e); break;
+        case 4: copy_elem<uint32_t>(d, e); break;
+        default: copy_elem<uint16_t>(d, e); break;
+        }
+    }
+}
+
+int launch_unpack_self(const igg_field &f, const SlabPack &pk, hipStream_t s)
+{
+    const int64_t nx = f.size[0], ny = f.size[1], nz = f.size[2];
+    const int64_t e = elem_bytes(f.dtype);
+    PlaneCopySet ps{};
+    int64_t maxcount = 0;
+    for (int d = 0; d < 2; ++d)
+        for (int side = 0; side < 2; ++side) {
+            PlaneCopy &c = ps.d[2 * d + side];
+            c.esz = (int)e;
+            c.src = (const unsigned char *)pk.send[d][side];
+            c.na = (int)nx;
+            c.sa = 1;
+            if (d == 0) {  // y plane: a = x, b = z, into row j
+                const int64_t j = side == 0 ? ny - 1 : 0;
+                c.dst = (unsigned char *)f.data + j * nx * e;
+                c.nb = (int)nz;
+                c.sb = nx * ny;
+            } else {  // z plane: a = x, b = y, into plane k
+                const int64_t k = side == 0 ? nz - 1 : 0;
+                c.dst = (unsigned char *)f.data + k * nx * ny * e;
+                c.nb = (int)ny;
+                c.sb = nx;
+            }
+            // whole rows as 16-byte vectors where the row length and base allow
+            if ((nx * e) % 16 == 0 && ((uintptr_t)f.data % 16) == 0) {
+                c.na = (int)(nx * e / 16);
+                c.sb = c.sb * e / 16;
+                c.esz = 16;
+            }
+            maxcount = std::max(maxcount, (int64_t)c.na * c.nb);
+        }
+    const int64_t b = (maxcount + 255) / 256;
+    dim3 grd((unsigned)std::min<int64_t>(std::max<int64_t>(b, 1), 1024), 4);
+    hipLaunchKernelGGL(k_unpack_planes, grd, dim3(256), 0, s, ps);
+    IGG_HIP(hipGetLastError());
+    return IGG_OK;
+}
+
 int launch_halo(const igg_field *fl, int nf, hipStream_t s, int dims)
 {
     Grid &g = grid();

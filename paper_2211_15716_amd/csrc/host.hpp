@@ -74,6 +74,8 @@ struct Grid {
     int schedule = -1;  // 1: slabs + update on the helper stream, 0: slabs first on the caller
                         // stream, 2: one chain on the caller stream, -1: 1 or 2 by size
     int fuse_x = 1;    // x exchange fused into the step kernels' stores
+    int slab_pack = 1;  // y/z halo planes packed by the boundary-slab kernel (one periodic rank)
+    int delay_where = 0, delay_iters = 0;  // IGG_TEST_DELAY: a fixed wait put into one stream
     int64_t zmarch_min = kZmarchMinPoints;  // smallest region for the z-march kernels
 
     // diffusion_run's graph: two steps T -> T2 -> T captured on the capture
@@ -133,13 +135,6 @@ struct XHalo {
     int64_t d_lo, d_hi;
 };
 
-// Global origin of a block for the FP16 stochastic-rounding hash: the point
-// (i, j, k) of the block is hashed as (i + ox, j + oy, k + oz) in a global
-// index space gnx points wide, so every decomposition rounds a point alike.
-struct SrOrigin {
-    int ox, oy, oz, gnx;
-};
-
 struct StepArgs {
     void *T2;
     const void *T;
@@ -154,6 +149,27 @@ struct StepArgs {
 int launch_step_boxes(int dtype, const StepArgs &a, const Box *b, int nb, hipStream_t s);
 int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s);
 int launch_step_boundary(int dtype, const StepArgs &a, const Split &sp, hipStream_t s);
+
+// The y and z halo planes of one rank that is its own neighbour in every
+// dimension, packed by the boundary-slab kernel as it computes them.
+// send[d][s] holds the plane of dimension d+1 (y, then z) sent to the lower
+// (s = 0: plane ol-1) or the upper (s = 1: plane n-ol) neighbour, x
+// fastest: nx*nz elements (y) or nx*ny (z).  Every entry, the plane's own
+// halo rows and columns included, ends up holding the value the
+// dimension-ordered halo update leaves at that point of its destination.
+struct SlabPack {
+    void *send[2][2];
+    int ol[3];
+};
+// The y and z slabs of sp (kind 1) with one wavefront per row run, marching
+// along the slab; with pk, the pack of the y and z halo planes fused in.
+int launch_step_slabs(int dtype, const StepArgs &a, const Split &sp, const SlabPack *pk, hipStream_t s);
+// Exchange and unpack of a SlabPack for the self-neighbour: each packed plane
+// is copied into the halo plane of f it fills (y plane side 0 -> j = ny-1,
+// side 1 -> j = 0; z likewise), one launch for the four planes.
+int launch_unpack_self(const igg_field &f, const SlabPack &pk, hipStream_t s);
+// Send buffer of rank r, slot f (a field index of the halo update), side.
+unsigned char *halo_send_plane(int r, int f, int side);
 
 struct AdjArgs {
     void *lam_n;

@@ -76,7 +76,7 @@ k_step_boxes(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__ 
     C out = diffuse<C>(c, widen<C>(T[p - 1]), widen<C>(T[p + 1]), widen<C>(T[p - sy]), widen<C>(T[p + sy]),
                        widen<C>(T[p - sz]), widen<C>(T[p + sz]), widen<C>(Ci[p]), a, rx, ry, rz);
     uint32_t r = 0;
-    if (stochastic) r = point_bits(plane_key(key, k + so.oz), i + so.ox, j + so.oy, so.gnx);
+    if (stochastic) r = sr_point_bits(sr_plane_key(key, k, so), i, j, so);
     const S v = Store<S>::put(out, r, stochastic);
     T2[p] = v;
     if (xh.on_lo && i == xh.lo) T2[p - i + nx - 1 + xh.d_lo] = v;
@@ -235,7 +235,7 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
             for (int q = 0; q < VEC; ++q) tile[buf][hyrow][1 + tx * VEC + q] = widen<C>(lane_elem<S, VEC>(yh, q));
         }
         __syncthreads();
-        const uint32_t pk = stochastic ? plane_key(key, k + z.so.oz) : 0u;
+        const uint32_t pk = stochastic ? sr_plane_key(key, k, z.so) : 0u;
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             if (!crow[r]) continue;
@@ -258,7 +258,7 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
                     ir = left ? ir + nx - z.w2 : ir - z.w2;
                     jreal = left ? jreal - 1 : jreal;
                 }
-                const uint32_t rb = stochastic ? point_bits(pk, ir + z.so.ox, jreal + z.so.oy, z.so.gnx) : 0u;
+                const uint32_t rb = stochastic ? sr_point_bits(pk, ir, jreal, z.so) : 0u;
                 set_elem<S, VEC>(out, q, Store<S>::put(v, rb, stochastic));
             }
             S *dst = T2 + (int64_t)k * sxy + col[r];
@@ -523,9 +523,294 @@ int launch_step_boundary(int dtype, const StepArgs &a, const Split &sp, hipStrea
             other[nother++] = sp.boundary[q];
     }
     int rc;
-    if (nother && (rc = launch_step_boxes(dtype, a, other, nother, s))) return rc;
+    if (nother && (rc = launch_step_slabs(dtype, a, sp, nullptr, s))) return rc;
     if (nxs && (rc = launch_xslabs(dtype, a, xs, nxs, s))) return rc;
     return IGG_OK;
+}
+
+
+// ------------------------------------------------------- boundary slabs
+// The y and z slabs of the boundary-first step: a few rows thick across one
+// dimension (the thin one), whole in x and in the other dimension.  One
+// wavefront takes a run of 64*VEC points of one row across its lanes and
+// marches along the slab's long in-plane dimension (z for a y slab, y for a
+// z slab).  Per point it holds T of the row one step behind, at and one step
+// ahead, and of the two neighbour rows across the thin dimension, in
+// registers, so each step reads three new rows of T (ahead, and both
+// neighbours): the least a slab one row thick can read.  x neighbours come
+// from the adjacent lanes by cross-lane shuffles, the two beyond the run's
+// ends from memory.  No LDS and no barriers: the waves of a work-group are
+// independent.
+//
+// With `pack` set (one rank, every dimension periodic: the process is its
+// own neighbour) the kernel also writes the y and z send planes of the halo
+// update as it computes their points: the pack of the update fused into the
+// stores, as the x exchange is.  An entry of a send plane that lies in an
+// x halo column, or in a halo row of the plane's other dimension, holds the
+// image of an inner point (the value the dimension-ordered update would
+// leave there), and the thread that computes that point stores it there
+// too.  So every entry of a packed plane is final, and the planes can be
+// unpacked in any order.
+struct SlabBox {
+    Box b;
+    int mz;         // 1: march along z (a y slab, rows j); 0: march along y (a z slab, rows k)
+    int nxs;        // runs of 64*VEC points per row
+    int nrow;       // rows across the thin dimension
+    int64_t first;  // first wave of this box
+};
+struct SlabSet {
+    SlabBox s[4];
+    int n;
+    int mc;  // march steps per chunk
+    int64_t waves;
+    int nx, ny, nz;
+    XHalo xh;
+    SrOrigin so;
+    int pack;
+    void *send[2][2];  // [0]: y planes, [1]: z planes; side 0 goes to the lower neighbour
+    int src[2][2];     // plane index packed into send[d][s] (ol-1 and n-ol)
+    int img[3][2];     // per dimension: the index whose image is n-1 (ol-1) and 0 (n-ol)
+};
+
+template <typename S, int VEC>
+__device__ __forceinline__ void slab_put_row(S *row, int i, bool xin, bool full, int i0, int i1,
+                                             const typename VecOf<S, VEC>::type &out)
+{
+    using V = typename VecOf<S, VEC>::type;
+    if (full) {
+        *reinterpret_cast<V *>(row + i) = out;
+    } else if (xin) {
+#pragma unroll
+        for (int q = 0; q < VEC; ++q)
+            if (i + q >= i0 && i + q < i1) row[i + q] = lane_elem<S, VEC>(out, q);
+    }
+}
+
+template <typename S, int VEC>
+__global__ void __launch_bounds__(256)
+k_step_slab(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__ Ci, SlabSet ss,
+            compute_t<S> a, compute_t<S> rx, compute_t<S> ry, compute_t<S> rz, uint32_t key, int stochastic)
+{
+    using C = compute_t<S>;
+    using V = typename VecOf<S, VEC>::type;
+    constexpr int RUN = 64 * VEC;
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (w >= ss.waves) return;
+    int q = 0;
+#pragma unroll
+    for (int p = 1; p < 4; ++p)
+        if (p < ss.n && w >= ss.s[p].first) q = p;
+    const Box bb = ss.s[q].b;
+    const int mz = ss.s[q].mz, nxs = ss.s[q].nxs, nrow = ss.s[q].nrow;
+    int64_t loc = w - ss.s[q].first;
+    const int xs = (int)(loc % nxs);
+    loc /= nxs;
+    const int row = (int)(loc % nrow);
+    const int ch = (int)(loc / nrow);
+
+    const int nx = ss.nx, ny = ss.ny;
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    const int x0 = xs * RUN;
+    const int i = x0 + lane * VEC;
+    const bool xin = i < nx;
+    const bool full = xin && i >= bb.i0 && i + VEC <= bb.i1;
+    // the row's fixed index across the thin dimension, the march range, and
+    // the strides across (st) and along (sm) the march
+    const int fixed = mz ? bb.j0 + row : bb.k0 + row;
+    const int mlo = mz ? bb.k0 : bb.j0, mhi = mz ? bb.k1 : bb.j1;
+    const int m0 = mlo + ch * ss.mc;
+    const int m1 = (m0 + ss.mc < mhi) ? m0 + ss.mc : mhi;
+    const int64_t st = mz ? sy : sz, sm = mz ? sz : sy;
+    int64_t p = mz ? (int64_t)fixed * sy + (int64_t)m0 * sz : (int64_t)m0 * sy + (int64_t)fixed * sz;
+
+    auto ld = [&](int64_t off) -> V {
+        V v{};
+        if (xin) v = *reinterpret_cast<const V *>(T + off + i);
+        return v;
+    };
+    // Ci is read once per step: non-temporal
+    auto ld_ci = [&](int64_t off) -> V {
+        V v{};
+        if (xin) v = __builtin_nontemporal_load(reinterpret_cast<const V *>(Ci + off + i));
+        return v;
+    };
+    // the x neighbour beyond the run's end: lane 0 holds x0-1, lane 63 x0+RUN
+    auto edge = [&](int64_t off) -> C {
+        C e = C(0);
+        if (lane == 0 && x0 > 0) e = widen<C>(T[off + x0 - 1]);
+        if (lane == 63 && x0 + RUN < nx) e = widen<C>(T[off + x0 + RUN]);
+        return e;
+    };
+
+    V tm = ld(p - sm), tc = ld(p), tp = ld(p + sm);
+    V rl = ld(p - st), rh = ld(p + st);
+    V ci = ld_ci(p);
+    C ec = edge(p);
+    for (int m = m0; m < m1; ++m) {
+        const bool more = m + 1 < m1;
+        V tn{}, rln{}, rhn{}, cn{};
+        C en = C(0);
+        if (more) {
+            tn = ld(p + 2 * sm);
+            rln = ld(p + sm - st);
+            rhn = ld(p + sm + st);
+            cn = ld_ci(p + sm);
+            en = edge(p + sm);
+        }
+        C fromlo = __shfl(widen<C>(lane_elem<S, VEC>(tc, VEC - 1)), lane > 0 ? lane - 1 : 0);
+        C fromhi = __shfl(widen<C>(lane_elem<S, VEC>(tc, 0)), lane < 63 ? lane + 1 : 63);
+        if (lane == 0) fromlo = ec;
+        if (lane == 63) fromhi = ec;
+        const int jc = mz ? fixed : m, kc = mz ? m : fixed;
+        const uint32_t pk = stochastic ? sr_plane_key(key, kc, ss.so) : 0u;
+        V out;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const C c = widen<C>(lane_elem<S, VEC>(tc, e));
+            const C xm = e == 0 ? fromlo : widen<C>(lane_elem<S, VEC>(tc, e - 1));
+            const C xp = e == VEC - 1 ? fromhi : widen<C>(lane_elem<S, VEC>(tc, e + 1));
+            const C across_m = widen<C>(lane_elem<S, VEC>(rl, e)), across_p = widen<C>(lane_elem<S, VEC>(rh, e));
+            const C along_m = widen<C>(lane_elem<S, VEC>(tm, e)), along_p = widen<C>(lane_elem<S, VEC>(tp, e));
+            const C ym = mz ? across_m : along_m, yp = mz ? across_p : along_p;
+            const C zm = mz ? along_m : across_m, zp = mz ? along_p : across_p;
+            const C v = diffuse<C>(c, xm, xp, ym, yp, zm, zp, widen<C>(lane_elem<S, VEC>(ci, e)), a, rx, ry, rz);
+            const uint32_t rb = stochastic ? sr_point_bits(pk, i + e, jc, ss.so) : 0u;
+            set_elem<S, VEC>(out, e, Store<S>::put(v, rb, stochastic));
+        }
+        S *dst = T2 + p;
+        if (full) {
+            __builtin_nontemporal_store(out, reinterpret_cast<V *>(dst + i));
+        } else if (xin) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+                if (i + e >= bb.i0 && i + e < bb.i1) dst[i + e] = lane_elem<S, VEC>(out, e);
+        }
+        // the x exchange fused into the stores, as in the other step kernels
+        if (ss.xh.on_lo && xin && i <= ss.xh.lo && i + VEC > ss.xh.lo)
+            dst[nx - 1 + ss.xh.d_lo] = lane_elem_dyn<S, VEC>(out, ss.xh.lo - i);
+        if (ss.xh.on_hi && xin && i <= ss.xh.hi && i + VEC > ss.xh.hi)
+            dst[ss.xh.d_hi] = lane_elem_dyn<S, VEC>(out, ss.xh.hi - i);
+        if (ss.pack) {
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                // d = 0: y planes (entries x + nx*k), d = 1: z planes (entries x + nx*j)
+                const int own = d == 0 ? jc : kc;
+                const int b = d == 0 ? kc : jc;
+                const int bn = d == 0 ? ss.nz : ny;
+                const int bd = d == 0 ? 2 : 1;
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    if (own != ss.src[d][side]) continue;
+                    S *P = reinterpret_cast<S *>(ss.send[d][side]);
+                    const int rows[3] = {b, b == ss.img[bd][0] ? bn - 1 : -1, b == ss.img[bd][1] ? 0 : -1};
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) {
+                        if (rows[r] < 0) continue;
+                        S *R = P + (int64_t)nx * rows[r];
+                        slab_put_row<S, VEC>(R, i, xin, full, bb.i0, bb.i1, out);
+                        if (xin && i <= ss.img[0][0] && i + VEC > ss.img[0][0])
+                            R[nx - 1] = lane_elem_dyn<S, VEC>(out, ss.img[0][0] - i);
+                        if (xin && i <= ss.img[0][1] && i + VEC > ss.img[0][1])
+                            R[0] = lane_elem_dyn<S, VEC>(out, ss.img[0][1] - i);
+                    }
+                }
+            }
+        }
+        tm = tc;
+        tc = tp;
+        tp = tn;
+        rl = rln;
+        rh = rhn;
+        ci = cn;
+        ec = en;
+        p += sm;
+    }
+}
+
+template <typename S, int VEC>
+static int run_slabs(const StepArgs &a, const Box *b, int nb, const SlabPack *pk, hipStream_t s)
+{
+    using C = compute_t<S>;
+    constexpr int RUN = 64 * VEC;
+    SlabSet ss{};
+    ss.nx = a.nx;
+    ss.ny = a.ny;
+    ss.nz = a.nz;
+    ss.xh = a.xh;
+    ss.so = a.so;
+    ss.n = nb;
+    // each box marches along the longer of its y and z extents
+    int64_t mlen[4], rows[4];
+    for (int q = 0; q < nb; ++q) {
+        SlabBox &sb = ss.s[q];
+        sb.b = b[q];
+        const int hy = b[q].j1 - b[q].j0, hz = b[q].k1 - b[q].k0;
+        sb.mz = hz >= hy;
+        sb.nxs = (a.nx + RUN - 1) / RUN;
+        sb.nrow = sb.mz ? hy : hz;
+        rows[q] = (int64_t)sb.nxs * sb.nrow;
+        mlen[q] = sb.mz ? hz : hy;
+    }
+    auto waves = [&](int mc) {
+        int64_t w = 0;
+        for (int q = 0; q < nb; ++q) w += rows[q] * ((mlen[q] + mc - 1) / mc);
+        return w;
+    };
+    int mc = env_int("IGG_SLAB_MARCH", 0);
+    if (mc < 1) {
+        // march chunks of 16 steps, halved (down to 2) while the launch has
+        // fewer than 4096 waves
+        mc = 16;
+        while (mc > 2 && waves(mc) < 4096) mc /= 2;
+    }
+    ss.mc = mc;
+    int64_t first = 0;
+    for (int q = 0; q < nb; ++q) {
+        ss.s[q].first = first;
+        first += rows[q] * ((mlen[q] + mc - 1) / mc);
+    }
+    ss.waves = first;
+    if (ss.waves == 0) return IGG_OK;
+    if (pk) {
+        ss.pack = 1;
+        for (int d = 0; d < 2; ++d)
+            for (int side = 0; side < 2; ++side) {
+                ss.send[d][side] = pk->send[d][side];
+                const int dim = d + 1;
+                ss.src[d][side] = side == 0 ? pk->ol[dim] - 1 : (dim == 1 ? a.ny : a.nz) - pk->ol[dim];
+            }
+        const int n3[3] = {a.nx, a.ny, a.nz};
+        for (int d = 0; d < 3; ++d) {
+            ss.img[d][0] = pk->ol[d] - 1;
+            ss.img[d][1] = n3[d] - pk->ol[d];
+        }
+    }
+    const int64_t blocks = (ss.waves + 3) / 4;
+    hipLaunchKernelGGL((k_step_slab<S, VEC>), dim3((unsigned)blocks), dim3(256), 0, s, (S *)a.T2, (const S *)a.T,
+                       (const S *)a.Ci, ss, (C)a.a, (C)a.rx, (C)a.ry, (C)a.rz, a.key, a.stochastic);
+    IGG_HIP(hipGetLastError());
+    return IGG_OK;
+}
+
+int launch_step_slabs(int dtype, const StepArgs &a, const Split &sp, const SlabPack *pk, hipStream_t s)
+{
+    Box yz[6];
+    int n = 0;
+    for (int q = 0; q < sp.nb; ++q)
+        if (sp.kind[q] == 1) yz[n++] = sp.boundary[q];
+    if (n == 0) return IGG_OK;
+    if (n > 4) return fail(IGG_ERR_ARG, "internal: more than four y/z slabs");
+    if (dtype == IGG_F64) {
+        if (vec_ok<double, 2>(a)) return run_slabs<double, 2>(a, yz, n, pk, s);
+        return run_slabs<double, 1>(a, yz, n, pk, s);
+    }
+    if (dtype == IGG_F32) {
+        if (vec_ok<float, 4>(a)) return run_slabs<float, 4>(a, yz, n, pk, s);
+        return run_slabs<float, 1>(a, yz, n, pk, s);
+    }
+    if (vec_ok<_Float16, 8>(a)) return run_slabs<_Float16, 8>(a, yz, n, pk, s);
+    return run_slabs<_Float16, 1>(a, yz, n, pk, s);
 }
 
 }  // namespace igg
