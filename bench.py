@@ -11,7 +11,9 @@ stored by the step kernels.  A step = one such call; K steps are timed after
 W warm-up steps, with inputs already resident in HBM.
 
 value = T_eff = (bytes of T read + Ci read + T2 written, each once per point)
-/ time per step, in GB/s (decimal).
+/ time per step, in GB/s (decimal), the time per step being the median of 20
+timings of K steps each (the paper's statistic); the first timed pass of K
+steps is reported beside it (ms_per_step_single_pass).
 
 Also reported on the same line:
   roofline      the inner-region step kernel: algorithmic bytes per launch
@@ -20,12 +22,22 @@ Also reported on the same line:
                 K steps (so the events do not perturb `value`), against the
                 8 TB/s HBM3E peak;
   ms_per_step_samples
-                20 more timings of K steps: median and its 95% interval;
+                the 20 timings of K steps: median and its 95% interval;
+  halo_overhead the split step's median over the median duration of the
+                step kernel alone on every inner point (the unsplit step's
+                kernel, without its halo update), minus 1; the unsplit
+                step's own median is in variants.f64_unsplit;
+  stream_ceiling_GBs
+                the library's streaming probe (igg_stream_probe) on 1 GiB
+                arrays for the read/write mixes of the step (2R1W), the
+                adjoint (4R2W) and the fused flux pass (2R4W): the rate a
+                plain stream reaches on this device;
   cpu_baseline  the CPU oracle on the host cores: 100 steps of the same
                 512^3 workload (bounded to about 10-30 s), as T_eff, and
                 one step on one core;
   variants      FP32 and FP16-storage steps at 512^3 (noisy-bump recipe,
-                uniform Ci) with their error against the FP64 result, the
+                uniform Ci) with their error against the FP64 oracle (the
+                GPU's FP64 result when the oracle is skipped), the
                 unsplit FP64 step, the checkpointed adjoint at 256^3, the
                 32^3 launch-bound step (eager and graph), and the 768^3
                 staggered flux form in FP32 with its checkpointed adjoint.
@@ -182,22 +194,26 @@ def oracle_256_timings(oracle, synth, nthreads):
     return res
 
 
-def step_samples(igg, torch, T, C, lam, dt, dx, dy, dz, steps, split, n):
-    """n more timings of `steps` steps each, continuing from T in fresh
-    buffers: median ms/step and the distribution-free 95% interval of the
-    median (order statistics; for n = 20 the 6th and 15th values)."""
+def step_samples(igg, torch, T, C, lam, dt, dx, dy, dz, steps, split, n, rnd_seed=None):
+    """n timings of `steps` steps each, continuing from T in fresh buffers
+    (FP16 stores rounded stochastically when rnd_seed is given): median
+    ms/step and the distribution-free 95% interval of the median (order
+    statistics; for n = 20 the 6th and 15th values)."""
     if n < 1 or steps < 1:
         return None
     from math import comb
     a, b = T.clone(), T.clone()
     vals = []
+    it = 0
     for _ in range(n):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record()
         for _ in range(steps):
-            igg.diffusion_step(b, a, C, lam, dt, dx, dy, dz, split=split)
+            rnd = igg.rounding("stochastic", rnd_seed, it) if rnd_seed is not None else None
+            igg.diffusion_step(b, a, C, lam, dt, dx, dy, dz, split=split, rnd=rnd)
             a, b = b, a
+            it += 1
         e1.record()
         torch.cuda.synchronize()
         vals.append(e0.elapsed_time(e1) / steps)
@@ -215,6 +231,64 @@ def step_samples(igg, torch, T, C, lam, dt, dx, dy, dz, steps, split, n):
     del a, b
     return {"n": n, "steps_each": steps, "median": round(med, 5), "ci95": [round(lo, 5), round(hi, 5)],
             "min": round(vals[0], 5), "max": round(vals[-1], 5)}
+
+
+def kernel_samples(igg, torch, T, C, lam, dt, dx, dy, dz, steps, n):
+    """n timings of `steps` unsplit steps with the library's kernel timing
+    events: the median duration of the step kernel over every inner point
+    (the step without its halo update), in ms."""
+    if n < 1 or steps < 1:
+        return None
+    a, b = T.clone(), T.clone()
+    vals = []
+    igg.timing_read()
+    igg.timing_enable(True)
+    for _ in range(n):
+        for _ in range(steps):
+            igg.diffusion_step(b, a, C, lam, dt, dx, dy, dz, split=None)
+            a, b = b, a
+        k_ms, k_launches, _, _ = igg.timing_read()
+        vals.append(k_ms / max(1, k_launches))
+    igg.timing_enable(False)
+    vals.sort()
+    del a, b
+    return vals[n // 2] if n % 2 else 0.5 * (vals[n // 2 - 1] + vals[n // 2])
+
+
+def stream_ceilings(igg, torch, n_doubles=1 << 27, reps=10):
+    """GB/s of the library's streaming probe for the step's, the adjoint's
+    and the fused flux pass's read/write mixes (and a plain copy), on arrays
+    of n_doubles doubles."""
+    out = {}
+    arrs = [torch.full((n_doubles,), 1.0 + q, dtype=torch.float64, device="cuda") for q in range(6)]
+    for name, nr, nw in (("1R1W", 1, 1), ("2R1W", 2, 1), ("4R2W", 4, 2), ("2R4W", 2, 4)):
+        src, dst = arrs[:nr], arrs[nr:nr + nw]
+        for _ in range(2):
+            igg.stream_probe(src, dst)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            igg.stream_probe(src, dst)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = round((nr + nw) * 8.0 * n_doubles * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del arrs
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_model():
+    """The host CPU's model name (Linux), or the platform's processor string."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def profile_adjoint(igg, torch, synth, n):
@@ -274,14 +348,18 @@ def main():
     Wb = T.clone()  # the second buffer starts as a copy (Fig. 1)
     log(f"timing {K} FP64 steps after {Wm} warm-up steps, split {args.split}")
     split = None if args.split == "none" else tuple(int(v) for v in args.split.split(","))
-    ms, out64, k_ms, k_pts, b_ms, ms_inst = time_steps(igg, torch, T, Wb, C, lam, dt, dx, dy, dz, K, Wm, split)
+    ms1, out64, k_ms, k_pts, b_ms, ms_inst = time_steps(igg, torch, T, Wb, C, lam, dt, dx, dy, dz, K, Wm, split)
     samples = step_samples(igg, torch, out64, C, lam, dt, dx, dy, dz, K, split, 0 if args.profile else args.samples)
+    # the step time is the median of the samples (the first pass alone when
+    # there are none)
+    ms = samples["median"] if samples else ms1
     teff = 24.0 * pts / (ms * 1e-3) / 1e9
     k_bytes = 24.0 * k_pts
     k_gbs = k_bytes / (k_ms * 1e-3) / 1e9
     khash = kernel_source_hash()
     traffic = traffic_from_profiles(khash, "inner_step_f64_512")
-    log(f"FP64: {ms:.4f} ms/step, T_eff {teff:.1f} GB/s; inner kernel {k_ms:.4f} ms, {k_gbs:.1f} GB/s")
+    log(f"FP64: {ms:.4f} ms/step (median; first pass {ms1:.4f}), T_eff {teff:.1f} GB/s; "
+        f"step kernel {k_ms:.4f} ms, {k_gbs:.1f} GB/s")
 
     result = {
         "metric": METRIC, "value": round(teff, 2), "unit": "GB/s", "n_gpus": 1, "steps": K,
@@ -293,12 +371,15 @@ def main():
                    "grid": [n, n, n], "nt_timed": K, "split": None if split is None else list(split), "dt": dt,
                    "bytes_per_point": 24, "parallelism": "1 GPU"},
         "hbm_frac": round(teff / HBM_PEAK_GBS, 4),
-        "roofline": {"bound": "hbm", "kernel": "k_step_zmarch<double> (inner region)",
+        "roofline": {"bound": "hbm",
+                     "kernel": "k_step_zmarch<double> (inner region; with the default one-launch schedule also "
+                               "the y/z boundary slabs, by its first work-groups)",
                      "achieved": round(k_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(k_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "bytes_per_launch": k_bytes, "points_per_launch": k_pts,
                      "ms_per_launch": round(k_ms, 5), "kernel_source_hash": khash},
         "halo_overhead": None,
+        "ms_per_step_single_pass": round(ms1, 5),
         "ms_per_step_samples": samples,
         "boundary_ms_per_step": round(b_ms, 5),
         "ms_per_step_with_kernel_events": round(ms_inst, 5),
@@ -315,32 +396,28 @@ def main():
         igg.finalize_global_grid()
         return
 
-    # ---------------------------------------------------------------- plain copy, the achievable ceiling
-    src = torch.empty(1 << 28, dtype=torch.float64, device="cuda").fill_(1.0)
-    dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(10):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 2 * src.numel() * 8 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    result["copy_probe_GBs"] = round(copy_gbs, 1)
-    log(f"plain device copy of 2 GiB: {copy_gbs:.1f} GB/s")
-    del src, dst
+    # ---------------------------------------------------------------- streaming ceiling of the mixes
+    result["stream_ceiling_GBs"] = stream_ceilings(igg, torch)
+    ceil = result["stream_ceiling_GBs"]["2R1W"]
+    result["roofline"]["frac_of_stream_ceiling"] = round(k_gbs / ceil, 4)
+    log(f"streaming probe (GB/s): {result['stream_ceiling_GBs']}")
 
     # ---------------------------------------------------------------- unsplit FP64 for comparison
-    T = T0_dev.clone()
-    ms_u, _, ku_ms, ku_pts, _, _ = time_steps(igg, torch, T, Wb, C, lam, dt, dx, dy, dz, min(K, 50), 5, None)
-    result["variants"] = {"f64_unsplit": {"ms_per_step": round(ms_u, 5),
+    nsu = max(1, args.samples)
+    u_samples = step_samples(igg, torch, T0_dev, C, lam, dt, dx, dy, dz, K, None, nsu)
+    ku_ms = kernel_samples(igg, torch, T0_dev, C, lam, dt, dx, dy, dz, K, nsu)
+    ms_u = u_samples["median"]
+    result["variants"] = {"f64_unsplit": {"ms_per_step": ms_u,
                                           "T_eff_GBs": round(24.0 * pts / (ms_u * 1e-3) / 1e9, 1),
-                                          "kernel_ms": round(ku_ms, 5)}}
+                                          "kernel_ms": round(ku_ms, 5), "ms_per_step_samples": u_samples}}
     # the halo update's step-time overhead: the split step against the step
-    # kernel over all inner points alone (the same computation, no update)
-    if split is not None and ku_pts == (n - 2) ** 3:
+    # kernel over all inner points alone (the same computation, no update),
+    # both medians of this run
+    if split is not None:
         result["halo_overhead"] = round(ms / ku_ms - 1.0, 4)
+        result["split_vs_unsplit_step"] = round(ms / ms_u, 4)
+    log(f"unsplit: step {ms_u:.4f} ms, kernel alone {ku_ms:.4f} ms (medians); "
+        f"split {ms:.4f} ms: halo overhead {result['halo_overhead']}")
 
     # ---------------------------------------------------------------- CPU oracle baseline
     gpu64 = None
@@ -378,7 +455,7 @@ def main():
                 break
         cpu_teff = 24.0 * pts * done / el / 1e9
         result["cpu_baseline"] = {"value": round(cpu_teff, 2), "unit": "GB/s", "cores": oracle.num_threads(),
-                                  "kind": "oracle",
+                                  "cpu_model": cpu_model(), "kind": "oracle",
                                   "sample": f"{done} steps of the {n}^3 FP64 workload (plain C loops, "
                                             f"OpenMP over z), {el:.1f} s"}
         if err is not None:
@@ -411,61 +488,74 @@ def main():
     igg.update_halo(T0_64, C_64)
     dt3 = igg.diffusion_dt(C_64, lam, dx, dy, dz)
     nt3 = 100
-    ref = None
+    # the reference of the error: the FP64 oracle after nt3 steps (the GPU's
+    # own FP64 run when the oracle leg is skipped)
+    ref_np, ref_kind = None, "gpu_f64"
+    if not args.no_cpu:
+        import oracle
+        T0h, Cih = w3["T0"].copy(), w3["Ci"].copy()
+        oracle.halo(T0h)
+        oracle.halo(Cih)
+        if oracle.time_step(dx, dy, dz, lam, oracle.max_all(Cih)) != dt3:
+            raise RuntimeError("GPU and oracle dt differ")
+        log(f"oracle: {nt3} steps of the precision-form workload (error reference)")
+        ref_np, ref_kind = oracle.run(T0h, Cih, nt3, lam, dt3, dx, dy, dz), "oracle"
+        del T0h, Cih
+
+    def run_nt3(Tv, Cv, seed, offset=0.0):
+        a, b = Tv.clone(), torch.empty_like(Tv)
+        for it in range(nt3):
+            rnd = igg.rounding("stochastic", seed, it) if seed is not None else None
+            igg.diffusion_step(b, a, Cv, lam, dt3, dx, dy, dz, split=SPLIT, rnd=rnd)
+            a, b = b, a
+        return a.to(torch.float64) + offset
+
+    def rel_err(final):
+        if ref_np is not None:
+            got = final.cpu().numpy()
+            i = (slice(1, -1),) * 3
+            return float(np.max(np.abs(got[i] - ref_np[i])) / np.max(np.abs(ref_np[i])))
+        d = (final - gpu_ref)[1:-1, 1:-1, 1:-1].abs().max().item()
+        return d / gpu_ref[1:-1, 1:-1, 1:-1].abs().max().item()
+
+    gpu_ref = None
     for name, tdt in (("f64", torch.float64), ("f32", torch.float32), ("f16", torch.float16)):
         Tv = T0_64.to(tdt).contiguous()
         Cv = C_64.to(tdt).contiguous()
         Wv = torch.empty_like(Tv)
         seed = 1234 if name == "f16" else None
-        # error run: exactly nt3 steps
-        outv = Tv.clone()
-        a, b = outv, torch.empty_like(Tv)
-        for it in range(nt3):
-            rnd = igg.rounding("stochastic", seed, it) if seed is not None else None
-            igg.diffusion_step(b, a, Cv, lam, dt3, dx, dy, dz, split=SPLIT, rnd=rnd)
-            a, b = b, a
-        final = a.to(torch.float64)
-        if name == "f64":
-            ref = final
-            err = 0.0
-        else:
-            d = (final - ref)[1:-1, 1:-1, 1:-1].abs().max().item()
-            err = d / ref[1:-1, 1:-1, 1:-1].abs().max().item()
-        msv, _, kv_ms, kv_pts, _, _ = time_steps(igg, torch, Tv.clone(), Wv, Cv, lam, dt3, dx, dy, dz, K, Wm,
-                                                 SPLIT, rnd_seed=seed)
+        final = run_nt3(Tv, Cv, seed)
+        if name == "f64" and ref_np is None:
+            gpu_ref = final
+        err = rel_err(final)
+        ms1v, _, kv_ms, kv_pts, _, _ = time_steps(igg, torch, Tv.clone(), Wv, Cv, lam, dt3, dx, dy, dz, K, Wm,
+                                                  SPLIT, rnd_seed=seed)
+        sv = step_samples(igg, torch, Tv, Cv, lam, dt3, dx, dy, dz, K, SPLIT, args.samples, rnd_seed=seed)
+        msv = sv["median"] if sv else ms1v
         s = Tv.element_size()
-        entry = {"ms_per_step": round(msv, 5), "T_eff_GBs": round(3 * s * pts / (msv * 1e-3) / 1e9, 1),
+        entry = {"ms_per_step": round(msv, 5), "ms_per_step_single_pass": round(ms1v, 5),
+                 "T_eff_GBs": round(3 * s * pts / (msv * 1e-3) / 1e9, 1),
                  "hbm_frac": round(3 * s * pts / (msv * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                 "inner_kernel_GBs": round(3 * s * kv_pts / (kv_ms * 1e-3) / 1e9, 1),
-                 "err_vs_f64": err, "nt_err": nt3}
+                 "kernel_GBs": round(3 * s * kv_pts / (kv_ms * 1e-3) / 1e9, 1),
+                 "err": err, "err_reference": ref_kind, "nt_err": nt3}
         if name == "f16":
             entry["rounding"] = "stochastic"
         result["variants"][name] = entry
-        log(f"{name}: {msv:.4f} ms/step, err vs FP64 {err:.3e}")
-        del Tv, Cv, Wv, outv, a, b, final
+        log(f"{name}: {msv:.4f} ms/step, err vs {ref_kind} {err:.3e}")
+        del Tv, Cv, Wv, final
     f32 = result["variants"]["f32"]
     result["variants"]["f32_speedup_vs_f64"] = round(result["variants"]["f64"]["ms_per_step"] / f32["ms_per_step"], 3)
     # FP16 with round-to-nearest stores, for comparison of the error
-    Tv = T0_64.to(torch.float16).contiguous()
     Cv = C_64.to(torch.float16).contiguous()
-    a, b = Tv, torch.empty_like(Tv)
-    for it in range(nt3):
-        igg.diffusion_step(b, a, Cv, lam, dt3, dx, dy, dz, split=SPLIT)
-        a, b = b, a
-    d = (a.to(torch.float64) - ref)[1:-1, 1:-1, 1:-1].abs().max().item()
-    result["variants"]["f16"]["err_vs_f64_round_nearest"] = d / ref[1:-1, 1:-1, 1:-1].abs().max().item()
+    result["variants"]["f16"]["err_round_nearest"] = rel_err(run_nt3(T0_64.to(torch.float16).contiguous(), Cv,
+                                                                     None))
     # FP16 storage of T - 1.7 with stochastic rounding: the step is linear and
     # a constant field is a fixed point, so stepping T - c gives the same
     # scheme; the smaller stored values keep finer absolute resolution
     off = 1.7
-    Tv = (T0_64 - off).to(torch.float16).contiguous()
-    a, b = Tv, torch.empty_like(Tv)
-    for it in range(nt3):
-        igg.diffusion_step(b, a, Cv, lam, dt3, dx, dy, dz, split=SPLIT, rnd=igg.rounding("stochastic", 1234, it))
-        a, b = b, a
-    d = (a.to(torch.float64) + off - ref)[1:-1, 1:-1, 1:-1].abs().max().item()
-    result["variants"]["f16"]["err_vs_f64_offset_1.7"] = d / ref[1:-1, 1:-1, 1:-1].abs().max().item()
-    del Tv, Cv, a, b, T0_64, C_64, ref
+    result["variants"]["f16"]["err_offset_1.7"] = rel_err(run_nt3((T0_64 - off).to(torch.float16).contiguous(), Cv,
+                                                                  1234, off))
+    del Cv, T0_64, C_64, gpu_ref, ref_np
     torch.cuda.empty_cache()
 
     igg.finalize_global_grid()

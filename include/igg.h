@@ -32,15 +32,21 @@
  *     shared halo buffers and are not supported.
  *   - Environment variables choose schedules and launch shapes only; no
  *     setting changes a result bit.  Read by igg_init_global_grid:
- *     IGG_SCHEDULE (0, 1 or 2: see diffusion_step; unset = by size and
+ *     IGG_SCHEDULE (0, 1, 2 or 3: see diffusion_step; unset = by size and
  *     type), IGG_X_EXCHANGE ("halo": x slabs and an x pass of the halo
  *     update instead of the x exchange stored by the step kernels),
- *     IGG_ZMARCH_MIN_POINTS (smallest region for the z-march kernels).
+ *     IGG_SLAB_PACK (0: the y and z halo planes move in a separate halo
+ *     pass; 1: the slab kernel packs them into send buffers and one copy
+ *     unpacks them; 2, the default: it stores them straight into the halo
+ *     planes), IGG_ZMARCH_MIN_POINTS (smallest region for the z-march
+ *     kernels), IGG_TEST_DELAY ("side:N", "inner:N" or "halo:N": a wait of
+ *     N rounds of about 3.4 us put into one stream of the split schedule,
+ *     for tests that the streams are ordered by events, not by timing).
  *     Read at each launch (tuning): IGG_FP64_MIDTILE_MAX_POINTS (regions
  *     below it take the 512-thread FP64 step tile), IGG_ZCHUNK, IGG_XCD_REMAP,
- *     IGG_XCD_BLOCK, IGG_XSLAB_ZCHUNK, IGG_XSLAB_REMAP, IGG_ADJ_ZCHUNK,
- *     IGG_ADJ_REMAP, IGG_ADJ_XCD_BLOCK, IGG_ADJ_WAVES, IGG_FLUX_ZCHUNK,
- *     IGG_FLUX_REMAP.
+ *     IGG_XCD_BLOCK, IGG_XSLAB_ZCHUNK, IGG_XSLAB_REMAP, IGG_SLAB_MARCH,
+ *     IGG_ADJ_ZCHUNK, IGG_ADJ_REMAP, IGG_ADJ_XCD_BLOCK, IGG_ADJ_WAVES,
+ *     IGG_FLUX_ZCHUNK, IGG_FLUX_REMAP.
  */
 #ifndef IGG_MI355X_H
 #define IGG_MI355X_H
@@ -191,15 +197,26 @@ int igg_finalize_global_grid(void);
  * element type; T must carry a valid halo (the previous step's update).
  *   split  boundary widths (Fig. 1 `@hide_communication (16, 2, 2)`), counted
  *          from the array edge including the halo plane, each >= overlap.
- *          The boundary slabs the halo update reads are computed first and
- *          the update of T2 follows them on the library's helper stream,
- *          while the inner region runs on `stream`, which finally waits for
- *          the helper.  The x exchange is stored by the step kernels as they
- *          compute the points it moves, so the x slabs are computed with the
- *          inner region.  Inner regions below 2^21 points, and FP16 fields
- *          (measured faster that way), run slabs, update and inner region as
- *          one chain on `stream`.
- *          NULL = no overlap: everything runs on `stream` in order.
+ *          The boundary slabs the halo update reads are computed first, and
+ *          the update of T2 follows them while the inner region is computed.
+ *          The x exchange is stored by the step kernels as they compute the
+ *          points it moves, so the x slabs are computed with the inner
+ *          region.  Schedules (IGG_SCHEDULE):
+ *            1  slabs, then the update, on the library's helper stream while
+ *               the inner region runs on `stream`, which finally waits for
+ *               the helper (the paper's arrangement);
+ *            0  slabs first on `stream`, the update on the helper stream;
+ *            2  slabs, update and inner region as one chain on `stream`;
+ *            3  on one rank that is periodic in every dimension: slabs and
+ *               inner region in one launch on `stream`, whose first
+ *               work-groups compute the slabs and store the y and z halo
+ *               planes of T2 as they go (with IGG_SLAB_PACK=1 they fill send
+ *               buffers that one copy then unpacks).
+ *          Default: 3 where it applies (measured fastest at 512^3, below the
+ *          unsplit step); otherwise 1 for inner regions of 2^21 points and
+ *          more in FP64/FP32, 2 for smaller ones and for FP16.
+ *          NULL = no overlap: the whole step, then the halo update, on
+ *          `stream`.
  *   rnd    FP16 store rounding, NULL = round to nearest even (ignored for
  *          FP64/FP32).
  * Arithmetic: FP64 for IGG_F64; FP32 for IGG_F32 and IGG_F16 with dt*lam and
@@ -365,6 +382,20 @@ int igg_plan_split(const int n[3], const int split[3], int boxes[7][6], int *nbo
  * IGG_ERR_HIP (enabling makes the event pool, so it needs the GPU). */
 int igg_timing_enable(int on);
 int igg_timing_read(double *ms, int64_t *launches, int64_t *points, double *boundary_ms);
+
+/* Streaming-bandwidth probe: the HBM rate a plain stream of a given
+ * read/write mix reaches on the current device, the achievable ceiling the
+ * stencil kernels are compared with beside the vendor peak.  For i < n:
+ * dst[w][i] = src[0][i] + ... + src[nsrc-1][i] (FP64) for every w, each
+ * array read or written once, with 16-byte non-temporal accesses and four
+ * independent vectors per thread.
+ *   src, dst   host arrays of nsrc (1..4) and ndst (1..4) device pointers to
+ *              n doubles each, 16-byte aligned; the caller owns them.
+ *   n          doubles per array, even.
+ * Needs no grid.  Asynchronous on `stream`.
+ * Errors: IGG_ERR_ARG (null or misaligned pointer, counts out of range),
+ * IGG_ERR_HIP. */
+int igg_stream_probe(const void *const *src, int nsrc, void *const *dst, int ndst, int64_t n, void *stream);
 
 /* Message for the calling thread's last failure ("" if none). */
 const char *igg_last_error(void);

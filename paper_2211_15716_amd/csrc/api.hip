@@ -284,23 +284,30 @@ static int check_spacings(double lam, double dt, double dx, double dy, double dz
 // inner region runs on the caller stream (as hide_communication does with
 // its boundary streams); schedule 0 runs the slabs on the caller stream ahead
 // of the inner region and only the update beside it; schedule 2 runs slabs,
-// update and inner region in that order on the caller stream.  By default
-// large inner regions take schedule 1; small grids are launch-bound, the
-// cross-stream fork and join cost more than the update they would hide, and
-// a captured graph of a single chain replays fastest, so they take schedule
-// 2.  FP16 fields take schedule 2 at any size: slabs running beside the
-// inner region made the 512^3 FP16 step 7% slower than the serial chain.
-// Callers whose inner kernel is partly latency-bound (the adjoint) pass
-// side_ok = false and take schedule 2 too: its slabs beside the inner
-// region cost 5.5% at 256^3 and 2% at 512^3.  When the x exchange is fused
-// into the stores (or x is not periodic) the update never reads the x
-// slabs, so they join the inner launch and the boundary phase is the y and
-// z slabs.
+// update and inner region in that order on the caller stream; schedule 3
+// (where the caller provides fused_launch) runs the slabs and the inner
+// region in one launch whose first work-groups take the slabs, and then
+// whatever halo update is left.  By default a caller with fused_launch (the
+// one-rank periodic step, whose slab kernel stores the y and z halo itself)
+// takes schedule 3: at 512^3 it is 0.8-2.6% faster than the unsplit step
+// while schedules 1 and 2 are slower, the slabs beside the inner launch
+// costing more bandwidth than the update they hide.  Otherwise large inner
+// regions take schedule 1; small grids are launch-bound, the cross-stream
+// fork and join cost more than the update they would hide, and a captured
+// graph of a single chain replays fastest, so they take schedule 2.  FP16
+// fields take schedule 2 at any size, as do callers whose inner kernel is
+// partly latency-bound (the adjoint passes side_ok = false): its slabs
+// beside the inner region cost 5.5% at 256^3 and 2% at 512^3.  When the x
+// exchange is fused into the stores (or x is not periodic) the update never
+// reads the x slabs, so they join the inner launch and the boundary phase is
+// the y and z slabs.
 // boundary(r, slabs, stream) and inner(r, box, stream) launch rank r's
 // kernels, halo(stream) the halo update of the results.
 template <typename HaloLaunch, typename BoundaryLaunch, typename InnerLaunch>
 static int run_split(const int *split, int dtype, HaloLaunch halo, BoundaryLaunch boundary,
-                     InnerLaunch inner_launch, hipStream_t s, bool side_ok = true)
+                     InnerLaunch inner_launch, hipStream_t s, bool side_ok = true,
+                     int (*fused_launch)(int, const Split &, const Box &, hipStream_t, void *) = nullptr,
+                     void *fused_ctx = nullptr)
 {
     Grid &g = grid();
     int rc;
@@ -319,7 +326,24 @@ static int run_split(const int *split, int dtype, HaloLaunch halo, BoundaryLaunc
         inner.i1 = g.n[0] - 1;
     }
     const bool side_pays = side_ok && box_points(inner) >= kSideMinPoints && dtype != IGG_F16;
-    const int sched = g.schedule >= 0 ? g.schedule : (side_pays ? 1 : 2);
+    int sched = g.schedule >= 0 ? g.schedule : (fused_launch ? 3 : side_pays ? 1 : 2);
+    if (sched == 3 && !fused_launch) sched = 2;
+    if (sched == 3) {
+        // one launch: the slab work-groups first, then the inner tiles; the
+        // halo update (if any is left after the fused pack) follows it
+        for (int r = 0; r < g.nranks; ++r) {
+            if ((rc = timing_mark(s, 0))) return rc;
+            if ((rc = fused_launch(r, bnd, inner, s, fused_ctx))) return rc;
+            if ((rc = timing_mark(s, 0))) return rc;
+            if (g.timing) {
+                g.t_launches++;
+                g.t_points += box_points(inner);
+                for (int q = 0; q < bnd.nb; ++q) g.t_points += box_points(bnd.boundary[q]);
+            }
+        }
+        if ((rc = test_delay(3, s))) return rc;
+        return halo(s);
+    }
     const bool on_side = sched == 1, serial = sched == 2;
     hipStream_t bs = on_side ? g.side : s;
     if (on_side) {
@@ -387,6 +411,18 @@ static int step_args(int r, const igg_field *T2, const igg_field *T, const igg_f
     return IGG_OK;
 }
 
+// The slabs and the inner region of one step in one launch (schedule 3).
+struct FusedStep {
+    int dtype;
+    const StepArgs *args;
+    const SlabPack *pk;
+};
+static int fused_step(int r, const Split &slabs, const Box &inner, hipStream_t s, void *ctx)
+{
+    const FusedStep &f = *static_cast<const FusedStep *>(ctx);
+    return launch_step_inner(f.dtype, f.args[r], inner, s, &slabs, f.pk);
+}
+
 // diffusion_step for the grid's nranks ranks: fields[r] is rank r's block.
 static int step_ranks(const igg_field *T2, const igg_field *T, const igg_field *Ci, double lam, double dt,
                       double dx, double dy, double dz, const int split[3], const igg_rounding *rnd,
@@ -450,10 +486,14 @@ static int step_ranks(const igg_field *T2, const igg_field *T, const igg_field *
         for (int d = 0; d < 2; ++d)
             for (int side = 0; side < 2; ++side) pk.send[d][side] = halo_send_plane(0, d, side);
         for (int d = 0; d < 3; ++d) pk.ol[d] = g.ol[d];
+        pk.direct = g.slab_pack == 2;
+        FusedStep ctx{dtype, args.data(), &pk};
         return run_split(
-            split, dtype, [&](hipStream_t st) { return launch_unpack_self(T2[0], pk, st); },
+            split, dtype,
+            [&](hipStream_t st) { return pk.direct ? IGG_OK : launch_unpack_self(T2[0], pk, st); },
             [&](int r, const Split &b, hipStream_t st) { return launch_step_slabs(dtype, args[r], b, &pk, st); },
-            [&](int r, const Box &b, hipStream_t st) { return launch_step_inner(dtype, args[r], b, st); }, s);
+            [&](int r, const Box &b, hipStream_t st) { return launch_step_inner(dtype, args[r], b, st); }, s, true,
+            fused_step, &ctx);
     }
     return run_split(
         split, dtype, [&](hipStream_t st) { return launch_halo(T2, 1, st, halo_dims); },
@@ -712,7 +752,7 @@ int igg_init_global_grid(int nx, int ny, int nz, const int dims[3], const int pe
     {
         const char *e = getenv("IGG_SCHEDULE");
         const int sv = (e && *e) ? atoi(e) : -1;
-        g.schedule = (sv >= 0 && sv <= 2) ? sv : -1;  // anything else: chosen by size and type
+        g.schedule = (sv >= 0 && sv <= 3) ? sv : -1;  // anything else: chosen by size and type
         const char *x = getenv("IGG_X_EXCHANGE");
         g.fuse_x = !(x && strcmp(x, "halo") == 0);
         // IGG_TEST_DELAY=<where>:<rounds>, where = side (before the helper
@@ -735,7 +775,8 @@ int igg_init_global_grid(int nx, int ny, int nz, const int dims[3], const int pe
             }
         }
         const char *sp = getenv("IGG_SLAB_PACK");
-        g.slab_pack = !(sp && strcmp(sp, "0") == 0);
+        const int spv = (sp && *sp) ? atoi(sp) : -1;
+        g.slab_pack = (spv >= 0 && spv <= 2) ? spv : 2;
         const char *zm = getenv("IGG_ZMARCH_MIN_POINTS");
         g.zmarch_min = (zm && *zm) ? atoll(zm) : kZmarchMinPoints;
     }

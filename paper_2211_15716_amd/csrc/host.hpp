@@ -74,7 +74,8 @@ struct Grid {
     int schedule = -1;  // 1: slabs + update on the helper stream, 0: slabs first on the caller
                         // stream, 2: one chain on the caller stream, -1: 1 or 2 by size
     int fuse_x = 1;    // x exchange fused into the step kernels' stores
-    int slab_pack = 1;  // y/z halo planes packed by the boundary-slab kernel (one periodic rank)
+    int slab_pack = 2;  // y/z halo planes packed by the boundary-slab kernel (one periodic rank):
+                        // 0 separate halo pass, 1 send planes + one unpack copy, 2 into the halo planes
     int delay_where = 0, delay_iters = 0;  // IGG_TEST_DELAY: a fixed wait put into one stream
     int64_t zmarch_min = kZmarchMinPoints;  // smallest region for the z-march kernels
 
@@ -147,7 +148,11 @@ struct StepArgs {
     SrOrigin so;
 };
 int launch_step_boxes(int dtype, const StepArgs &a, const Box *b, int nb, hipStream_t s);
-int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s);
+struct SlabPack;
+// The inner region b; with `slabs`, the y and z slabs of that split (and the
+// pack pk) run in the same launch, by its first work-groups.
+int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s, const Split *slabs = nullptr,
+                      const SlabPack *pk = nullptr);
 int launch_step_boundary(int dtype, const StepArgs &a, const Split &sp, hipStream_t s);
 
 // The y and z halo planes of one rank that is its own neighbour in every
@@ -160,6 +165,7 @@ int launch_step_boundary(int dtype, const StepArgs &a, const Split &sp, hipStrea
 struct SlabPack {
     void *send[2][2];
     int ol[3];
+    int direct;  // 1: store straight into the halo planes of T2 (no send buffers, no unpack)
 };
 // The y and z slabs of sp (kind 1) with one wavefront per row run, marching
 // along the slab; with pk, the pack of the y and z halo planes fused in.

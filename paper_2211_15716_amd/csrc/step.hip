@@ -83,6 +83,216 @@ k_step_boxes(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__ 
     if (xh.on_hi && i == xh.hi) T2[p - i + xh.d_hi] = v;
 }
 
+// ------------------------------------------------------- boundary slabs
+// The y and z slabs of the boundary-first step: a few rows thick across one
+// dimension (the thin one), whole in x and in the other dimension.  One
+// wavefront takes a run of 64*VEC points of one row across its lanes and
+// marches along the slab's long in-plane dimension (z for a y slab, y for a
+// z slab).  Per point it holds T of the row one step behind, at and one step
+// ahead, and of the two neighbour rows across the thin dimension, in
+// registers, so each step reads three new rows of T (ahead, and both
+// neighbours): the least a slab one row thick can read.  x neighbours come
+// from the adjacent lanes by cross-lane shuffles, the two beyond the run's
+// ends from memory.  No LDS and no barriers: the waves of a work-group are
+// independent.
+//
+// With `pack` set (one rank, every dimension periodic: the process is its
+// own neighbour) the kernel also writes the y and z send planes of the halo
+// update as it computes their points: the pack of the update fused into the
+// stores, as the x exchange is.  An entry of a send plane that lies in an
+// x halo column, or in a halo row of the plane's other dimension, holds the
+// image of an inner point (the value the dimension-ordered update would
+// leave there), and the thread that computes that point stores it there
+// too.  So every entry of a packed plane is final, and the planes can be
+// unpacked in any order.  With `direct` packing the planes are the halo
+// planes of T2 they fill: the exchange with oneself and the unpack become
+// these stores, as for the x exchange.
+struct SlabBox {
+    Box b;
+    int mz;         // 1: march along z (a y slab, rows j); 0: march along y (a z slab, rows k)
+    int nxs;        // runs of 64*VEC points per row
+    int nrow;       // rows across the thin dimension
+    int64_t first;  // first wave of this box
+};
+struct SlabSet {
+    SlabBox s[4];
+    int n;
+    int mc;  // march steps per chunk
+    int64_t waves;
+    int nx, ny, nz;
+    XHalo xh;
+    SrOrigin so;
+    int pack;
+    void *send[2][2];    // [0]: y planes, [1]: z planes; side 0 goes to the lower neighbour
+    int64_t bstride[2];  // elements between consecutive rows of a y / z plane
+    int src[2][2];       // plane index packed into send[d][s] (ol-1 and n-ol)
+    int img[3][2];     // per dimension: the index whose image is n-1 (ol-1) and 0 (n-ol)
+};
+
+template <typename S, int VEC>
+__device__ __forceinline__ void slab_put_row(S *row, int i, bool xin, bool full, int i0, int i1,
+                                             const typename VecOf<S, VEC>::type &out)
+{
+    using V = typename VecOf<S, VEC>::type;
+    if (full) {
+        *reinterpret_cast<V *>(row + i) = out;
+    } else if (xin) {
+#pragma unroll
+        for (int q = 0; q < VEC; ++q)
+            if (i + q >= i0 && i + q < i1) row[i + q] = lane_elem<S, VEC>(out, q);
+    }
+}
+
+// Wave w of the slab work (lane `lane`); waves past the end return.
+template <typename S, int VEC>
+__device__ __forceinline__ void slab_body(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__ Ci,
+                                          const SlabSet &ss, compute_t<S> a, compute_t<S> rx, compute_t<S> ry,
+                                          compute_t<S> rz, uint32_t key, int stochastic, int64_t w, int lane)
+{
+    using C = compute_t<S>;
+    using V = typename VecOf<S, VEC>::type;
+    constexpr int RUN = 64 * VEC;
+    if (w >= ss.waves) return;
+    int q = 0;
+#pragma unroll
+    for (int p = 1; p < 4; ++p)
+        if (p < ss.n && w >= ss.s[p].first) q = p;
+    const Box bb = ss.s[q].b;
+    const int mz = ss.s[q].mz, nxs = ss.s[q].nxs, nrow = ss.s[q].nrow;
+    int64_t loc = w - ss.s[q].first;
+    const int xs = (int)(loc % nxs);
+    loc /= nxs;
+    const int row = (int)(loc % nrow);
+    const int ch = (int)(loc / nrow);
+
+    const int nx = ss.nx, ny = ss.ny;
+    const int64_t sy = nx, sz = (int64_t)nx * ny;
+    const int x0 = xs * RUN;
+    const int i = x0 + lane * VEC;
+    const bool xin = i < nx;
+    const bool full = xin && i >= bb.i0 && i + VEC <= bb.i1;
+    // the row's fixed index across the thin dimension, the march range, and
+    // the strides across (st) and along (sm) the march
+    const int fixed = mz ? bb.j0 + row : bb.k0 + row;
+    const int mlo = mz ? bb.k0 : bb.j0, mhi = mz ? bb.k1 : bb.j1;
+    const int m0 = mlo + ch * ss.mc;
+    const int m1 = (m0 + ss.mc < mhi) ? m0 + ss.mc : mhi;
+    const int64_t st = mz ? sy : sz, sm = mz ? sz : sy;
+    int64_t p = mz ? (int64_t)fixed * sy + (int64_t)m0 * sz : (int64_t)m0 * sy + (int64_t)fixed * sz;
+
+    auto ld = [&](int64_t off) -> V {
+        V v{};
+        if (xin) v = *reinterpret_cast<const V *>(T + off + i);
+        return v;
+    };
+    // Ci is read once per step: non-temporal
+    auto ld_ci = [&](int64_t off) -> V {
+        V v{};
+        if (xin) v = __builtin_nontemporal_load(reinterpret_cast<const V *>(Ci + off + i));
+        return v;
+    };
+    // the x neighbour beyond the run's end: lane 0 holds x0-1, lane 63 x0+RUN
+    auto edge = [&](int64_t off) -> C {
+        C e = C(0);
+        if (lane == 0 && x0 > 0) e = widen<C>(T[off + x0 - 1]);
+        if (lane == 63 && x0 + RUN < nx) e = widen<C>(T[off + x0 + RUN]);
+        return e;
+    };
+
+    V tm = ld(p - sm), tc = ld(p), tp = ld(p + sm);
+    V rl = ld(p - st), rh = ld(p + st);
+    V ci = ld_ci(p);
+    C ec = edge(p);
+    for (int m = m0; m < m1; ++m) {
+        const bool more = m + 1 < m1;
+        V tn{}, rln{}, rhn{}, cn{};
+        C en = C(0);
+        if (more) {
+            tn = ld(p + 2 * sm);
+            rln = ld(p + sm - st);
+            rhn = ld(p + sm + st);
+            cn = ld_ci(p + sm);
+            en = edge(p + sm);
+        }
+        C fromlo = __shfl(widen<C>(lane_elem<S, VEC>(tc, VEC - 1)), lane > 0 ? lane - 1 : 0);
+        C fromhi = __shfl(widen<C>(lane_elem<S, VEC>(tc, 0)), lane < 63 ? lane + 1 : 63);
+        if (lane == 0) fromlo = ec;
+        if (lane == 63) fromhi = ec;
+        const int jc = mz ? fixed : m, kc = mz ? m : fixed;
+        const uint32_t pk = stochastic ? sr_plane_key(key, kc, ss.so) : 0u;
+        V out;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+            const C c = widen<C>(lane_elem<S, VEC>(tc, e));
+            const C xm = e == 0 ? fromlo : widen<C>(lane_elem<S, VEC>(tc, e - 1));
+            const C xp = e == VEC - 1 ? fromhi : widen<C>(lane_elem<S, VEC>(tc, e + 1));
+            const C across_m = widen<C>(lane_elem<S, VEC>(rl, e)), across_p = widen<C>(lane_elem<S, VEC>(rh, e));
+            const C along_m = widen<C>(lane_elem<S, VEC>(tm, e)), along_p = widen<C>(lane_elem<S, VEC>(tp, e));
+            const C ym = mz ? across_m : along_m, yp = mz ? across_p : along_p;
+            const C zm = mz ? along_m : across_m, zp = mz ? along_p : across_p;
+            const C v = diffuse<C>(c, xm, xp, ym, yp, zm, zp, widen<C>(lane_elem<S, VEC>(ci, e)), a, rx, ry, rz);
+            const uint32_t rb = stochastic ? sr_point_bits(pk, i + e, jc, ss.so) : 0u;
+            set_elem<S, VEC>(out, e, Store<S>::put(v, rb, stochastic));
+        }
+        S *dst = T2 + p;
+        if (full) {
+            __builtin_nontemporal_store(out, reinterpret_cast<V *>(dst + i));
+        } else if (xin) {
+#pragma unroll
+            for (int e = 0; e < VEC; ++e)
+                if (i + e >= bb.i0 && i + e < bb.i1) dst[i + e] = lane_elem<S, VEC>(out, e);
+        }
+        // the x exchange fused into the stores, as in the other step kernels
+        if (ss.xh.on_lo && xin && i <= ss.xh.lo && i + VEC > ss.xh.lo)
+            dst[nx - 1 + ss.xh.d_lo] = lane_elem_dyn<S, VEC>(out, ss.xh.lo - i);
+        if (ss.xh.on_hi && xin && i <= ss.xh.hi && i + VEC > ss.xh.hi)
+            dst[ss.xh.d_hi] = lane_elem_dyn<S, VEC>(out, ss.xh.hi - i);
+        if (ss.pack) {
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                // d = 0: y planes (entries x + nx*k), d = 1: z planes (entries x + nx*j)
+                const int own = d == 0 ? jc : kc;
+                const int b = d == 0 ? kc : jc;
+                const int bn = d == 0 ? ss.nz : ny;
+                const int bd = d == 0 ? 2 : 1;
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+                    if (own != ss.src[d][side]) continue;
+                    S *P = reinterpret_cast<S *>(ss.send[d][side]);
+                    const int rows[3] = {b, b == ss.img[bd][0] ? bn - 1 : -1, b == ss.img[bd][1] ? 0 : -1};
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) {
+                        if (rows[r] < 0) continue;
+                        S *R = P + ss.bstride[d] * rows[r];
+                        slab_put_row<S, VEC>(R, i, xin, full, bb.i0, bb.i1, out);
+                        if (xin && i <= ss.img[0][0] && i + VEC > ss.img[0][0])
+                            R[nx - 1] = lane_elem_dyn<S, VEC>(out, ss.img[0][0] - i);
+                        if (xin && i <= ss.img[0][1] && i + VEC > ss.img[0][1])
+                            R[0] = lane_elem_dyn<S, VEC>(out, ss.img[0][1] - i);
+                    }
+                }
+            }
+        }
+        tm = tc;
+        tc = tp;
+        tp = tn;
+        rl = rln;
+        rh = rhn;
+        ci = cn;
+        ec = en;
+        p += sm;
+    }
+}
+
+template <typename S, int VEC>
+__global__ void __launch_bounds__(256)
+k_step_slab(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__ Ci, SlabSet ss,
+            compute_t<S> a, compute_t<S> rx, compute_t<S> ry, compute_t<S> rz, uint32_t key, int stochastic)
+{
+    slab_body<S, VEC>(T2, T, Ci, ss, a, rx, ry, rz, key, stochastic,
+                      (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), threadIdx.x & 63);
+}
+
 // --------------------------------------------------------------- z-march
 // Up to two boxes per launch: work-groups [0, split_block) tile box 0, the
 // rest tile box 1 (the two x slabs of the boundary go in one launch).
@@ -108,6 +318,10 @@ struct ZTile {
     int w2, wl0, wl1, wr0, wr1, jr0, jr1, wh;
     XHalo xh;
     SrOrigin so;
+    // boundary slabs in the same launch: work-groups [0, slab_blocks) run
+    // the slab waves of ss (dispatched first), the rest tile the boxes
+    int64_t slab_blocks;
+    SlabSet ss;
 };
 
 // BX x TY threads; thread (tx, ty) owns RY consecutive rows of VEC points.
@@ -127,14 +341,23 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
 
     const int tx = threadIdx.x % BX, ty = threadIdx.x / BX;
     int64_t g = blockIdx.x;
+    if constexpr (!WRAP) {
+        if (g < z.slab_blocks) {
+            slab_body<S, VEC>(T2, T, Ci, z.ss, a, rx, ry, rz, key, stochastic,
+                              g * (BX * TY / 64) + (int64_t)(threadIdx.x / 64), threadIdx.x & 63);
+            return;
+        }
+    }
+    g -= z.slab_blocks;
+    const int64_t nblk = gridDim.x - z.slab_blocks;
     if (z.remap == 1) {
-        g = xcd_remap(g, gridDim.x);
+        g = xcd_remap(g, nblk);
     } else if (z.remap >= 2) {
         // keep each x-row of tiles on one XCD (work-group g runs on XCD g % 8),
         // so neighbouring tiles read each other's edge lines from the same L2;
         // mode 2 deals rows to XCDs in turn, mode 3 in contiguous ranges
         const int64_t ntx0 = z.box[0].ntx, B = z.rblock;
-        const int64_t P = gridDim.x / ntx0, P8 = z.remap == 2 ? P / (8 * B) * (8 * B) : P / 8 * 8;
+        const int64_t P = nblk / ntx0, P8 = z.remap == 2 ? P / (8 * B) * (8 * B) : P / 8 * 8;
         if (g < ntx0 * P8) {
             const int64_t x = g % 8, slot = g / 8;
             const int64_t q = slot / ntx0;
@@ -369,9 +592,94 @@ static const ZLaunch kInnerF16 = {16, "IGG_ZCHUNK", 3, "IGG_XCD_REMAP", 8192};
 // x slabs: 8 planes, contiguous ranges of tile rows per XCD
 static const ZLaunch kXSlab = {8, "IGG_XSLAB_ZCHUNK", 3, "IGG_XSLAB_REMAP", 2048};
 
+// The slab work of boxes b (y and z slabs) for runs of 64*VEC points, with
+// the fused pack when pk is given.
+// mc_fixed > 0: march chunks of that many steps (unless IGG_SLAB_MARCH is set).
+template <typename S, int VEC>
+static SlabSet make_slabset(const StepArgs &a, const Box *b, int nb, const SlabPack *pk, int mc_fixed = 0)
+{
+    constexpr int RUN = 64 * VEC;
+    SlabSet ss{};
+    ss.nx = a.nx;
+    ss.ny = a.ny;
+    ss.nz = a.nz;
+    ss.xh = a.xh;
+    ss.so = a.so;
+    ss.n = nb;
+    // each box marches along the longer of its y and z extents
+    int64_t mlen[4], rows[4];
+    for (int q = 0; q < nb; ++q) {
+        SlabBox &sb = ss.s[q];
+        sb.b = b[q];
+        const int hy = b[q].j1 - b[q].j0, hz = b[q].k1 - b[q].k0;
+        sb.mz = hz >= hy;
+        sb.nxs = (a.nx + RUN - 1) / RUN;
+        sb.nrow = sb.mz ? hy : hz;
+        rows[q] = (int64_t)sb.nxs * sb.nrow;
+        mlen[q] = sb.mz ? hz : hy;
+    }
+    auto waves = [&](int mc) {
+        int64_t w = 0;
+        for (int q = 0; q < nb; ++q) w += rows[q] * ((mlen[q] + mc - 1) / mc);
+        return w;
+    };
+    int mc = env_int("IGG_SLAB_MARCH", mc_fixed);
+    if (mc < 1) {
+        // march chunks of 16 steps, halved (down to 2) while the launch has
+        // fewer than 4096 waves
+        mc = 16;
+        while (mc > 2 && waves(mc) < 4096) mc /= 2;
+    }
+    ss.mc = mc;
+    int64_t first = 0;
+    for (int q = 0; q < nb; ++q) {
+        ss.s[q].first = first;
+        first += rows[q] * ((mlen[q] + mc - 1) / mc);
+    }
+    ss.waves = first;
+    if (pk) {
+        ss.pack = 1;
+        const int64_t e = sizeof(S), nx = a.nx, ny = a.ny, nz = a.nz;
+        for (int d = 0; d < 2; ++d)
+            for (int side = 0; side < 2; ++side) {
+                if (pk->direct) {
+                    // the halo plane the sent plane fills: y side 0 -> j = ny-1,
+                    // side 1 -> j = 0; z likewise
+                    const int64_t plane = side == 0 ? (d == 0 ? ny - 1 : nz - 1) : 0;
+                    ss.send[d][side] = (unsigned char *)a.T2 + plane * (d == 0 ? nx : nx * ny) * e;
+                    ss.bstride[d] = d == 0 ? nx * ny : nx;
+                } else {
+                    ss.send[d][side] = pk->send[d][side];
+                    ss.bstride[d] = nx;
+                }
+                const int dim = d + 1;
+                ss.src[d][side] = side == 0 ? pk->ol[dim] - 1 : (dim == 1 ? a.ny : a.nz) - pk->ol[dim];
+            }
+        const int n3[3] = {a.nx, a.ny, a.nz};
+        for (int d = 0; d < 3; ++d) {
+            ss.img[d][0] = pk->ol[d] - 1;
+            ss.img[d][1] = n3[d] - pk->ol[d];
+        }
+    }
+    return ss;
+}
+
+template <typename S, int VEC>
+static int run_slabs(const StepArgs &a, const Box *b, int nb, const SlabPack *pk, hipStream_t s)
+{
+    using C = compute_t<S>;
+    const SlabSet ss = make_slabset<S, VEC>(a, b, nb, pk);
+    if (ss.waves == 0) return IGG_OK;
+    const int64_t blocks = (ss.waves + 3) / 4;
+    hipLaunchKernelGGL((k_step_slab<S, VEC>), dim3((unsigned)blocks), dim3(256), 0, s, (S *)a.T2, (const S *)a.T,
+                       (const S *)a.Ci, ss, (C)a.a, (C)a.rx, (C)a.ry, (C)a.rz, a.key, a.stochastic);
+    IGG_HIP(hipGetLastError());
+    return IGG_OK;
+}
+
 template <typename S, int VEC, int BX, int TY, int RY, int WRAP = 0>
 static int run_zmarch(const StepArgs &a, const Box *b, int nbox, hipStream_t s, const ZLaunch &L,
-                      const ZTile *wrap = nullptr)
+                      const ZTile *wrap = nullptr, const SlabSet *slabs = nullptr)
 {
     using C = compute_t<S>;
     constexpr int TW = BX * VEC, BY = TY * RY;
@@ -407,6 +715,11 @@ static int run_zmarch(const StepArgs &a, const Box *b, int nbox, hipStream_t s, 
         blocks += nb;
     }
     if (nbox == 1) z.box[1] = z.box[0];
+    if (slabs && slabs->waves > 0) {
+        z.ss = *slabs;
+        z.slab_blocks = (slabs->waves + (BX * TY / 64) - 1) / (BX * TY / 64);
+        blocks += z.slab_blocks;
+    }
     if (blocks == 0) return IGG_OK;
     // a wrapped tile addresses its arrays from w2 points before each row
     const int64_t off = WRAP ? z.w2 : 0;
@@ -434,9 +747,37 @@ static bool vec_ok(const StepArgs &a)
 // These shapes and work-group mappings measured fastest on MI355X at 512^3.
 // Rows whose length does not allow vector loads take one point per lane;
 // regions below zmarch_min_points() take the box kernel.
-int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s)
+// One inner-region launch, with the slab waves of yz (nyz boxes) run by
+// the launch's first work-groups when nyz > 0.
+template <typename S, int VEC, int BX, int TY, int RY>
+static int run_inner(const StepArgs &a, const Box &b, hipStream_t s, const ZLaunch &L, const Box *yz, int nyz,
+                     const SlabPack *pk)
 {
-    if (box_count(b) < zmarch_min_points()) return launch_step_boxes(dtype, a, &b, 1, s);
+    if (nyz == 0) return run_zmarch<S, VEC, BX, TY, RY>(a, &b, 1, s, L);
+    // march chunks measured fastest for the launch at 512^3 (the slab waves
+    // share it with the inner tiles, so their count matters less than the
+    // rows each reloads per chunk): FP64 8 steps (0.5412 ms per step against
+    // 0.5459 with 2), FP32 2 (0.2930 against 0.3036 with 8), FP16 4
+    const int mc = sizeof(S) == 8 ? 8 : sizeof(S) == 4 ? 2 : 4;
+    const SlabSet ss = make_slabset<S, VEC>(a, yz, nyz, pk, mc);
+    return run_zmarch<S, VEC, BX, TY, RY>(a, &b, 1, s, L, nullptr, &ss);
+}
+
+int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s, const Split *slabs,
+                      const SlabPack *pk)
+{
+    Box yz[6];
+    int nyz = 0;
+    if (slabs)
+        for (int q = 0; q < slabs->nb; ++q)
+            if (slabs->kind[q] == 1) yz[nyz++] = slabs->boundary[q];
+    if (nyz > 4) return fail(IGG_ERR_ARG, "internal: more than four y/z slabs");
+    if (box_count(b) < zmarch_min_points()) {
+        // small grids: the slabs first, then the box kernel
+        int rc;
+        if (nyz && (rc = launch_step_slabs(dtype, a, *slabs, pk, s))) return rc;
+        return box_count(b) > 0 ? launch_step_boxes(dtype, a, &b, 1, s) : IGG_OK;
+    }
     if (dtype == IGG_F64) {
         if (vec_ok<double, 2>(a)) {
             // the same 128 x 16 tile over 512 threads of 2 rows (108 registers,
@@ -445,17 +786,17 @@ int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s)
             static const char *kMidEnv = "IGG_FP64_MIDTILE_MAX_POINTS";
             const char *e = getenv(kMidEnv);
             const int64_t mid_max = (e && *e) ? atoll(e) : ((int64_t)1 << 26);
-            if (box_count(b) < mid_max) return run_zmarch<double, 2, 64, 8, 2>(a, &b, 1, s, kInner);
-            return run_zmarch<double, 2, 64, 4, 4>(a, &b, 1, s, kInner);
+            if (box_count(b) < mid_max) return run_inner<double, 2, 64, 8, 2>(a, b, s, kInner, yz, nyz, pk);
+            return run_inner<double, 2, 64, 4, 4>(a, b, s, kInner, yz, nyz, pk);
         }
-        return run_zmarch<double, 1, 64, 8, 2>(a, &b, 1, s, kInner);
+        return run_inner<double, 1, 64, 8, 2>(a, b, s, kInner, yz, nyz, pk);
     }
     if (dtype == IGG_F32) {
-        if (vec_ok<float, 4>(a)) return run_zmarch<float, 4, 64, 8, 2>(a, &b, 1, s, kInnerRanges);
-        return run_zmarch<float, 1, 64, 8, 2>(a, &b, 1, s, kInner);
+        if (vec_ok<float, 4>(a)) return run_inner<float, 4, 64, 8, 2>(a, b, s, kInnerRanges, yz, nyz, pk);
+        return run_inner<float, 1, 64, 8, 2>(a, b, s, kInner, yz, nyz, pk);
     }
-    if (vec_ok<_Float16, 4>(a)) return run_zmarch<_Float16, 4, 64, 4, 2>(a, &b, 1, s, kInnerF16);
-    return run_zmarch<_Float16, 1, 64, 8, 2>(a, &b, 1, s, kInnerF16);
+    if (vec_ok<_Float16, 4>(a)) return run_inner<_Float16, 4, 64, 4, 2>(a, b, s, kInnerF16, yz, nyz, pk);
+    return run_inner<_Float16, 1, 64, 8, 2>(a, b, s, kInnerF16, yz, nyz, pk);
 }
 
 // x slabs (computed first only when the x exchange is a separate pass of
@@ -528,270 +869,6 @@ int launch_step_boundary(int dtype, const StepArgs &a, const Split &sp, hipStrea
     return IGG_OK;
 }
 
-
-// ------------------------------------------------------- boundary slabs
-// The y and z slabs of the boundary-first step: a few rows thick across one
-// dimension (the thin one), whole in x and in the other dimension.  One
-// wavefront takes a run of 64*VEC points of one row across its lanes and
-// marches along the slab's long in-plane dimension (z for a y slab, y for a
-// z slab).  Per point it holds T of the row one step behind, at and one step
-// ahead, and of the two neighbour rows across the thin dimension, in
-// registers, so each step reads three new rows of T (ahead, and both
-// neighbours): the least a slab one row thick can read.  x neighbours come
-// from the adjacent lanes by cross-lane shuffles, the two beyond the run's
-// ends from memory.  No LDS and no barriers: the waves of a work-group are
-// independent.
-//
-// With `pack` set (one rank, every dimension periodic: the process is its
-// own neighbour) the kernel also writes the y and z send planes of the halo
-// update as it computes their points: the pack of the update fused into the
-// stores, as the x exchange is.  An entry of a send plane that lies in an
-// x halo column, or in a halo row of the plane's other dimension, holds the
-// image of an inner point (the value the dimension-ordered update would
-// leave there), and the thread that computes that point stores it there
-// too.  So every entry of a packed plane is final, and the planes can be
-// unpacked in any order.
-struct SlabBox {
-    Box b;
-    int mz;         // 1: march along z (a y slab, rows j); 0: march along y (a z slab, rows k)
-    int nxs;        // runs of 64*VEC points per row
-    int nrow;       // rows across the thin dimension
-    int64_t first;  // first wave of this box
-};
-struct SlabSet {
-    SlabBox s[4];
-    int n;
-    int mc;  // march steps per chunk
-    int64_t waves;
-    int nx, ny, nz;
-    XHalo xh;
-    SrOrigin so;
-    int pack;
-    void *send[2][2];  // [0]: y planes, [1]: z planes; side 0 goes to the lower neighbour
-    int src[2][2];     // plane index packed into send[d][s] (ol-1 and n-ol)
-    int img[3][2];     // per dimension: the index whose image is n-1 (ol-1) and 0 (n-ol)
-};
-
-template <typename S, int VEC>
-__device__ __forceinline__ void slab_put_row(S *row, int i, bool xin, bool full, int i0, int i1,
-                                             const typename VecOf<S, VEC>::type &out)
-{
-    using V = typename VecOf<S, VEC>::type;
-    if (full) {
-        *reinterpret_cast<V *>(row + i) = out;
-    } else if (xin) {
-#pragma unroll
-        for (int q = 0; q < VEC; ++q)
-            if (i + q >= i0 && i + q < i1) row[i + q] = lane_elem<S, VEC>(out, q);
-    }
-}
-
-template <typename S, int VEC>
-__global__ void __launch_bounds__(256)
-k_step_slab(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__ Ci, SlabSet ss,
-            compute_t<S> a, compute_t<S> rx, compute_t<S> ry, compute_t<S> rz, uint32_t key, int stochastic)
-{
-    using C = compute_t<S>;
-    using V = typename VecOf<S, VEC>::type;
-    constexpr int RUN = 64 * VEC;
-    const int lane = threadIdx.x & 63;
-    const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (w >= ss.waves) return;
-    int q = 0;
-#pragma unroll
-    for (int p = 1; p < 4; ++p)
-        if (p < ss.n && w >= ss.s[p].first) q = p;
-    const Box bb = ss.s[q].b;
-    const int mz = ss.s[q].mz, nxs = ss.s[q].nxs, nrow = ss.s[q].nrow;
-    int64_t loc = w - ss.s[q].first;
-    const int xs = (int)(loc % nxs);
-    loc /= nxs;
-    const int row = (int)(loc % nrow);
-    const int ch = (int)(loc / nrow);
-
-    const int nx = ss.nx, ny = ss.ny;
-    const int64_t sy = nx, sz = (int64_t)nx * ny;
-    const int x0 = xs * RUN;
-    const int i = x0 + lane * VEC;
-    const bool xin = i < nx;
-    const bool full = xin && i >= bb.i0 && i + VEC <= bb.i1;
-    // the row's fixed index across the thin dimension, the march range, and
-    // the strides across (st) and along (sm) the march
-    const int fixed = mz ? bb.j0 + row : bb.k0 + row;
-    const int mlo = mz ? bb.k0 : bb.j0, mhi = mz ? bb.k1 : bb.j1;
-    const int m0 = mlo + ch * ss.mc;
-    const int m1 = (m0 + ss.mc < mhi) ? m0 + ss.mc : mhi;
-    const int64_t st = mz ? sy : sz, sm = mz ? sz : sy;
-    int64_t p = mz ? (int64_t)fixed * sy + (int64_t)m0 * sz : (int64_t)m0 * sy + (int64_t)fixed * sz;
-
-    auto ld = [&](int64_t off) -> V {
-        V v{};
-        if (xin) v = *reinterpret_cast<const V *>(T + off + i);
-        return v;
-    };
-    // Ci is read once per step: non-temporal
-    auto ld_ci = [&](int64_t off) -> V {
-        V v{};
-        if (xin) v = __builtin_nontemporal_load(reinterpret_cast<const V *>(Ci + off + i));
-        return v;
-    };
-    // the x neighbour beyond the run's end: lane 0 holds x0-1, lane 63 x0+RUN
-    auto edge = [&](int64_t off) -> C {
-        C e = C(0);
-        if (lane == 0 && x0 > 0) e = widen<C>(T[off + x0 - 1]);
-        if (lane == 63 && x0 + RUN < nx) e = widen<C>(T[off + x0 + RUN]);
-        return e;
-    };
-
-    V tm = ld(p - sm), tc = ld(p), tp = ld(p + sm);
-    V rl = ld(p - st), rh = ld(p + st);
-    V ci = ld_ci(p);
-    C ec = edge(p);
-    for (int m = m0; m < m1; ++m) {
-        const bool more = m + 1 < m1;
-        V tn{}, rln{}, rhn{}, cn{};
-        C en = C(0);
-        if (more) {
-            tn = ld(p + 2 * sm);
-            rln = ld(p + sm - st);
-            rhn = ld(p + sm + st);
-            cn = ld_ci(p + sm);
-            en = edge(p + sm);
-        }
-        C fromlo = __shfl(widen<C>(lane_elem<S, VEC>(tc, VEC - 1)), lane > 0 ? lane - 1 : 0);
-        C fromhi = __shfl(widen<C>(lane_elem<S, VEC>(tc, 0)), lane < 63 ? lane + 1 : 63);
-        if (lane == 0) fromlo = ec;
-        if (lane == 63) fromhi = ec;
-        const int jc = mz ? fixed : m, kc = mz ? m : fixed;
-        const uint32_t pk = stochastic ? sr_plane_key(key, kc, ss.so) : 0u;
-        V out;
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-            const C c = widen<C>(lane_elem<S, VEC>(tc, e));
-            const C xm = e == 0 ? fromlo : widen<C>(lane_elem<S, VEC>(tc, e - 1));
-            const C xp = e == VEC - 1 ? fromhi : widen<C>(lane_elem<S, VEC>(tc, e + 1));
-            const C across_m = widen<C>(lane_elem<S, VEC>(rl, e)), across_p = widen<C>(lane_elem<S, VEC>(rh, e));
-            const C along_m = widen<C>(lane_elem<S, VEC>(tm, e)), along_p = widen<C>(lane_elem<S, VEC>(tp, e));
-            const C ym = mz ? across_m : along_m, yp = mz ? across_p : along_p;
-            const C zm = mz ? along_m : across_m, zp = mz ? along_p : across_p;
-            const C v = diffuse<C>(c, xm, xp, ym, yp, zm, zp, widen<C>(lane_elem<S, VEC>(ci, e)), a, rx, ry, rz);
-            const uint32_t rb = stochastic ? sr_point_bits(pk, i + e, jc, ss.so) : 0u;
-            set_elem<S, VEC>(out, e, Store<S>::put(v, rb, stochastic));
-        }
-        S *dst = T2 + p;
-        if (full) {
-            __builtin_nontemporal_store(out, reinterpret_cast<V *>(dst + i));
-        } else if (xin) {
-#pragma unroll
-            for (int e = 0; e < VEC; ++e)
-                if (i + e >= bb.i0 && i + e < bb.i1) dst[i + e] = lane_elem<S, VEC>(out, e);
-        }
-        // the x exchange fused into the stores, as in the other step kernels
-        if (ss.xh.on_lo && xin && i <= ss.xh.lo && i + VEC > ss.xh.lo)
-            dst[nx - 1 + ss.xh.d_lo] = lane_elem_dyn<S, VEC>(out, ss.xh.lo - i);
-        if (ss.xh.on_hi && xin && i <= ss.xh.hi && i + VEC > ss.xh.hi)
-            dst[ss.xh.d_hi] = lane_elem_dyn<S, VEC>(out, ss.xh.hi - i);
-        if (ss.pack) {
-#pragma unroll
-            for (int d = 0; d < 2; ++d) {
-                // d = 0: y planes (entries x + nx*k), d = 1: z planes (entries x + nx*j)
-                const int own = d == 0 ? jc : kc;
-                const int b = d == 0 ? kc : jc;
-                const int bn = d == 0 ? ss.nz : ny;
-                const int bd = d == 0 ? 2 : 1;
-#pragma unroll
-                for (int side = 0; side < 2; ++side) {
-                    if (own != ss.src[d][side]) continue;
-                    S *P = reinterpret_cast<S *>(ss.send[d][side]);
-                    const int rows[3] = {b, b == ss.img[bd][0] ? bn - 1 : -1, b == ss.img[bd][1] ? 0 : -1};
-#pragma unroll
-                    for (int r = 0; r < 3; ++r) {
-                        if (rows[r] < 0) continue;
-                        S *R = P + (int64_t)nx * rows[r];
-                        slab_put_row<S, VEC>(R, i, xin, full, bb.i0, bb.i1, out);
-                        if (xin && i <= ss.img[0][0] && i + VEC > ss.img[0][0])
-                            R[nx - 1] = lane_elem_dyn<S, VEC>(out, ss.img[0][0] - i);
-                        if (xin && i <= ss.img[0][1] && i + VEC > ss.img[0][1])
-                            R[0] = lane_elem_dyn<S, VEC>(out, ss.img[0][1] - i);
-                    }
-                }
-            }
-        }
-        tm = tc;
-        tc = tp;
-        tp = tn;
-        rl = rln;
-        rh = rhn;
-        ci = cn;
-        ec = en;
-        p += sm;
-    }
-}
-
-template <typename S, int VEC>
-static int run_slabs(const StepArgs &a, const Box *b, int nb, const SlabPack *pk, hipStream_t s)
-{
-    using C = compute_t<S>;
-    constexpr int RUN = 64 * VEC;
-    SlabSet ss{};
-    ss.nx = a.nx;
-    ss.ny = a.ny;
-    ss.nz = a.nz;
-    ss.xh = a.xh;
-    ss.so = a.so;
-    ss.n = nb;
-    // each box marches along the longer of its y and z extents
-    int64_t mlen[4], rows[4];
-    for (int q = 0; q < nb; ++q) {
-        SlabBox &sb = ss.s[q];
-        sb.b = b[q];
-        const int hy = b[q].j1 - b[q].j0, hz = b[q].k1 - b[q].k0;
-        sb.mz = hz >= hy;
-        sb.nxs = (a.nx + RUN - 1) / RUN;
-        sb.nrow = sb.mz ? hy : hz;
-        rows[q] = (int64_t)sb.nxs * sb.nrow;
-        mlen[q] = sb.mz ? hz : hy;
-    }
-    auto waves = [&](int mc) {
-        int64_t w = 0;
-        for (int q = 0; q < nb; ++q) w += rows[q] * ((mlen[q] + mc - 1) / mc);
-        return w;
-    };
-    int mc = env_int("IGG_SLAB_MARCH", 0);
-    if (mc < 1) {
-        // march chunks of 16 steps, halved (down to 2) while the launch has
-        // fewer than 4096 waves
-        mc = 16;
-        while (mc > 2 && waves(mc) < 4096) mc /= 2;
-    }
-    ss.mc = mc;
-    int64_t first = 0;
-    for (int q = 0; q < nb; ++q) {
-        ss.s[q].first = first;
-        first += rows[q] * ((mlen[q] + mc - 1) / mc);
-    }
-    ss.waves = first;
-    if (ss.waves == 0) return IGG_OK;
-    if (pk) {
-        ss.pack = 1;
-        for (int d = 0; d < 2; ++d)
-            for (int side = 0; side < 2; ++side) {
-                ss.send[d][side] = pk->send[d][side];
-                const int dim = d + 1;
-                ss.src[d][side] = side == 0 ? pk->ol[dim] - 1 : (dim == 1 ? a.ny : a.nz) - pk->ol[dim];
-            }
-        const int n3[3] = {a.nx, a.ny, a.nz};
-        for (int d = 0; d < 3; ++d) {
-            ss.img[d][0] = pk->ol[d] - 1;
-            ss.img[d][1] = n3[d] - pk->ol[d];
-        }
-    }
-    const int64_t blocks = (ss.waves + 3) / 4;
-    hipLaunchKernelGGL((k_step_slab<S, VEC>), dim3((unsigned)blocks), dim3(256), 0, s, (S *)a.T2, (const S *)a.T,
-                       (const S *)a.Ci, ss, (C)a.a, (C)a.rx, (C)a.ry, (C)a.rz, a.key, a.stochastic);
-    IGG_HIP(hipGetLastError());
-    return IGG_OK;
-}
 
 int launch_step_slabs(int dtype, const StepArgs &a, const Split &sp, const SlabPack *pk, hipStream_t s)
 {

@@ -36,7 +36,7 @@ EXPORTS = ["igg_init_global_grid", "igg_global_size", "igg_topology", "igg_updat
            "igg_timing_enable", "igg_timing_read", "igg_last_error", "igg_version",
            "igg_nranks", "igg_rank_coords", "igg_neighbors", "igg_update_halo_ranks", "diffusion_step_ranks",
            "diffusion_step_adjoint_ranks", "diffusion_flux_step_ranks", "diffusion_flux_step_adjoint_ranks",
-           "diffusion_run"]
+           "diffusion_run", "igg_stream_probe"]
 
 
 class IggError(RuntimeError):
@@ -96,6 +96,8 @@ def load():
     lib.igg_plan_split.argtypes = [_PI, _PI, (ctypes.c_int * 6) * 7, _PI]
     lib.igg_timing_enable.argtypes = [ctypes.c_int]
     lib.igg_timing_read.argtypes = [ctypes.POINTER(d), i64p, i64p, ctypes.POINTER(d)]
+    lib.igg_stream_probe.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(vp), ctypes.c_int,
+                                     ctypes.c_int64, vp]
     lib.igg_last_error.restype = ctypes.c_char_p
     lib.igg_version.restype = ctypes.c_char_p
     _lib_handle = lib
@@ -335,6 +337,18 @@ def timing_read():
     _check(load().igg_timing_read(ctypes.byref(ms), ctypes.byref(launches), ctypes.byref(points),
                                   ctypes.byref(bms)))
     return ms.value, launches.value, points.value, bms.value
+
+
+def stream_probe(srcs, dsts, stream=None):
+    """dst = sum of srcs for every dst (FP64 device tensors of one size): the
+    streaming probe of the given read/write mix."""
+    n = srcs[0].numel()
+    for t in list(srcs) + list(dsts):
+        if t.dtype.itemsize != 8 or t.numel() != n or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("probe arrays are contiguous 8-byte device tensors of one size")
+    sa = (ctypes.c_void_p * len(srcs))(*[t.data_ptr() for t in srcs])
+    da = (ctypes.c_void_p * len(dsts))(*[t.data_ptr() for t in dsts])
+    _check(load().igg_stream_probe(sa, len(srcs), da, len(dsts), n, _stream(stream)))
 
 
 def version():

@@ -279,3 +279,24 @@ def test_rank_solvers_check_block_count_and_overlaps(host_grid):
             diffusion.loss_and_grad_ranks([t, t], [t, t], [t, t], None, 2)
     finally:
         igg.finalize_global_grid()
+
+
+@no_gpu
+def test_stream_probe_validates_before_any_hip_call():
+    """The streaming probe refuses bad counts, null and misaligned pointers
+    on the host; zero elements launch nothing."""
+    lib = igg.load()
+    VP = ctypes.c_void_p
+    ok = (VP * 4)(0x10000000, 0x10001000, 0x10002000, 0x10003000)
+    bad = (VP * 1)(0x10000008 + 4)
+    null = (VP * 1)(None)
+    assert lib.igg_stream_probe(ok, 0, ok, 1, 16, None) == igg.IGG_ERR_ARG
+    assert lib.igg_stream_probe(ok, 5, ok, 1, 16, None) == igg.IGG_ERR_ARG
+    assert lib.igg_stream_probe(ok, 1, ok, 5, 16, None) == igg.IGG_ERR_ARG
+    assert lib.igg_stream_probe(ok, 2, ok, 1, 15, None) == igg.IGG_ERR_ARG
+    assert lib.igg_stream_probe(bad, 1, ok, 1, 16, None) == igg.IGG_ERR_ARG
+    assert lib.igg_stream_probe(null, 1, ok, 1, 16, None) == igg.IGG_ERR_ARG
+    assert lib.igg_stream_probe(None, 1, ok, 1, 16, None) == igg.IGG_ERR_ARG
+    lib.igg_stream_probe(bad, 1, ok, 1, 16, None)
+    assert "aligned" in lib.igg_last_error().decode()
+    assert lib.igg_stream_probe(ok, 2, ok, 2, 0, None) == igg.IGG_OK

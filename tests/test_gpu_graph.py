@@ -13,11 +13,13 @@ from gpu_common import dev, grid, host, say  # noqa: E402
 
 @pytest.mark.parametrize("n,split,sched", [((32, 32, 32), (16, 2, 2), None), ((66, 40, 36), (16, 2, 2), None),
                                            ((48, 40, 36), None, None), ((66, 40, 36), (16, 2, 2), "1"),
-                                           ((66, 40, 36), (16, 2, 2), "0"), ((160, 140, 120), (16, 2, 2), None)])
+                                           ((66, 40, 36), (16, 2, 2), "0"), ((66, 40, 36), (16, 2, 2), "2"),
+                                           ((160, 140, 120), (16, 2, 2), None), ((160, 140, 120), (16, 2, 2), "1")])
 def test_graph_replay_matches_eager(n, split, sched, monkeypatch):
     """Every schedule is capturable: the helper-stream forms (1, and 0)
-    capture their fork and join events as graph edges; 160x140x120 takes
-    schedule 1 by default."""
+    capture their fork and join events as graph edges; the one-launch form
+    (3, the default for these one-rank periodic grids) and the serial chain
+    (2) capture as a chain."""
     if sched is not None:
         monkeypatch.setenv("IGG_SCHEDULE", sched)
     say("graph", n, split, sched)
@@ -89,12 +91,15 @@ def test_native_graph_run_matches_eager(n, split, dt_name):
 
 
 @pytest.mark.parametrize("split", [(4, 3, 3), None])
-def test_kernel_timing_events_count_launches_and_points(split):
+@pytest.mark.parametrize("sched", ["1", "3"])
+def test_kernel_timing_events_count_launches_and_points(split, sched, monkeypatch):
     """The library's kernel timing (the figures the benchmark's roofline
     takes): with timing on, each step adds one inner launch of the expected
-    number of points and a positive duration; a read resets the totals;
-    more launches than the pre-made event pool grow it; with timing off
-    nothing is counted; and timing does not change a result bit."""
+    number of points (in the one-launch schedule the slabs' points too) and
+    a positive duration; a read resets the totals; more launches than the
+    pre-made event pool grow it; with timing off nothing is counted; and
+    timing does not change a result bit."""
+    monkeypatch.setenv("IGG_SCHEDULE", sched)
     n = (40, 36, 34)
     nx, ny, nz = n
     rng = np.random.default_rng(71)
@@ -104,7 +109,8 @@ def test_kernel_timing_events_count_launches_and_points(split):
     oracle.halo(Ci)
     dx = 1.0 / (nx - 1)
     dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
-    if split is None:
+    side = split is not None and sched == "1"
+    if not side:  # everything in the one launch
         pts = (nx - 2) * (ny - 2) * (nz - 2)
     else:  # x slabs join the inner launch; y and z slabs are the boundary
         pts = (nx - 2) * (ny - 2 * split[1]) * (nz - 2 * split[2])
@@ -118,7 +124,7 @@ def test_kernel_timing_events_count_launches_and_points(split):
         assert torch.equal(out, ref)
         assert launches == 6 and points == 6 * pts
         assert ms > 0.0
-        assert (bms > 0.0) == (split is not None)
+        assert (bms > 0.0) == side
         assert igg.timing_read() == (0.0, 0, 0, 0.0)
         # more timed launches than the 2048 events made up front
         diffusion.forward(T.clone(), C, 1100, 1.0, dt, dx, dx, dx, split=split)

@@ -51,7 +51,7 @@ def test_translation_equivariance(dt_name):
 
 
 @pytest.mark.parametrize("where", ["side:300", "inner:300", "halo:300"])
-@pytest.mark.parametrize("pack", ["1", "0"])
+@pytest.mark.parametrize("pack", ["1", "2", "0"])
 def test_held_back_stream_gives_same_bits(where, pack, monkeypatch):
     """A fixed wait of about a millisecond (longer than a step here) put into
     the helper stream before the slabs, into the caller stream before the
@@ -69,7 +69,7 @@ def test_held_back_stream_gives_same_bits(where, pack, monkeypatch):
     with grid(n, zmarch_min=None):
         ref = host(diffusion.forward(dev(T0), dev(Ci), nt, 1.0, dt, *d, split=(16, 2, 2)))
     monkeypatch.setenv("IGG_TEST_DELAY", where)
-    for sched in ("1", "0", "2"):
+    for sched in ("1", "0", "2", "3"):
         monkeypatch.setenv("IGG_SCHEDULE", sched)
         with grid(n, zmarch_min=None):
             say("held back", where, "pack", pack, "schedule", sched)
@@ -84,8 +84,11 @@ def test_held_back_stream_gives_same_bits(where, pack, monkeypatch):
 @pytest.mark.parametrize("ol,split", [((2, 2, 2), (16, 2, 2)), ((3, 3, 3), (16, 4, 3)), ((2, 3, 4), (5, 3, 4))])
 def test_fused_pack_equals_separate_halo_pass(dt_name, ol, split, monkeypatch):
     """The boundary-slab kernel packing the y and z planes (and their halo
-    entries' images) with one exchange-and-unpack copy gives the bits of the
-    separate pack, exchange and unpack passes, halos included."""
+    entries' images) with one exchange-and-unpack copy, or storing them
+    straight into the halo planes, gives the bits of the separate pack,
+    exchange and unpack passes, halos included, with the slabs on the helper
+    stream, before the inner region on the caller stream, or in the inner
+    region's launch."""
     n = (132, 40, 36)
     T0, Ci = synth.noisy_state_uniform_ci(*n, seed=85, noise=1e-2)
     oracle.halo(T0, ol)
@@ -93,14 +96,17 @@ def test_fused_pack_equals_separate_halo_pass(dt_name, ol, split, monkeypatch):
     d = (1 / 131, 1 / 39, 1 / 35)
     dt = oracle.time_step(*d, 1.0, oracle.max_all(Ci))
     outs = []
-    for pack in ("1", "0"):
-        monkeypatch.setenv("IGG_SLAB_PACK", pack)
-        with grid(n, overlaps=ol):
-            say("pack", pack, dt_name, ol, split)
-            o = diffusion.forward(dev(T0, DT[dt_name]), dev(Ci, DT[dt_name]), 5, 1.0, dt, *d, split=split,
-                                  sr_seed=5 if dt_name == "f16" else None)
-            outs.append(host(o))
-    assert np.array_equal(outs[0], outs[1])
+    for pack in ("1", "2", "0"):
+        for sched in ("1", "2", "3"):
+            monkeypatch.setenv("IGG_SLAB_PACK", pack)
+            monkeypatch.setenv("IGG_SCHEDULE", sched)
+            with grid(n, overlaps=ol):
+                say("pack", pack, "schedule", sched, dt_name, ol, split)
+                o = diffusion.forward(dev(T0, DT[dt_name]), dev(Ci, DT[dt_name]), 5, 1.0, dt, *d, split=split,
+                                      sr_seed=5 if dt_name == "f16" else None)
+                outs.append(host(o))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
     ref = oracle.run(T0, Ci, 5, 1.0, dt, *d, ol=ol)
     tol = {"f64": 1e-12, "f32": 1e-5, "f16": 2e-3}[dt_name]
     assert np.max(np.abs(outs[0] - ref)) <= tol * np.max(np.abs(ref))

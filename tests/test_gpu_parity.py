@@ -207,7 +207,7 @@ def test_schedules_and_x_exchange_forms_bit_exact(dt_name, monkeypatch):
     dx = 1.0 / (nx - 1)
     dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
     outs = []
-    for sched in ("1", "0", "2"):
+    for sched in ("1", "0", "2", "3"):
         for xform in ("fused", "halo"):
             monkeypatch.setenv("IGG_SCHEDULE", sched)
             monkeypatch.setenv("IGG_X_EXCHANGE", xform)
