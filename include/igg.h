@@ -359,6 +359,24 @@ int diffusion_flux_step_adjoint_ranks(const igg_field *lam_n, const igg_field *l
  * IGG_ERR_DTYPE, IGG_ERR_HIP. */
 int igg_reduce(int op, const igg_field *a, const igg_field *b, double *out, void *stream);
 
+/* igg_reduce for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same reduction over the same points with the same kernels, so the same
+ * bits as igg_reduce, but:
+ *   out_dev  device pointer to one double (caller-owned), written on
+ *            `stream`; the call does not synchronise and returns once the
+ *            work is queued.
+ *   - No allocation of any kind: the partial results go to a static device
+ *     array of 1024 doubles (8 KiB per device, held until the process
+ *     ends), which bounds the work-groups of one reduction at 1024 (every
+ *     reduction fits; IGG_ERR_SIZE otherwise); the grid's own buffers and
+ *     streams are neither made nor used (only igg_init_global_grid is
+ *     needed, for the size checks).
+ *   - Every call on a device shares that array: calls that overlap in time
+ *     on one device (unordered streams, several host threads) race.
+ * Errors: as igg_reduce (IGG_ERR_ARG for a null out_dev). */
+int igg_reduce_noalloc(int op, const igg_field *a, const igg_field *b, double *out_dev, void *stream);
+
 /* --------------------------------------------------------- host helpers */
 
 /* The boundary-first partition used by diffusion_step for grid size n and

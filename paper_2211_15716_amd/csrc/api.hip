@@ -1077,7 +1077,9 @@ int diffusion_flux_step_adjoint_ranks(const igg_field *lam_n, const igg_field *l
     return adjoint_step(1, lam_n, lam_np1, T_n, Ci, gCi, lam, dt, dx, dy, dz, split, stream);
 }
 
-int igg_reduce(int op, const igg_field *a, const igg_field *b, double *out, void *stream)
+// Argument checks of igg_reduce and igg_reduce_noalloc (host only); *two is
+// set when the operation reads b.
+static int check_reduce(int op, const igg_field *a, const igg_field *b, const double *out, bool *two)
 {
     Grid &g = grid();
     if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
@@ -1085,16 +1087,31 @@ int igg_reduce(int op, const igg_field *a, const igg_field *b, double *out, void
     if (op < IGG_RED_MAX || op > IGG_RED_MAX_ABS) return fail(IGG_ERR_ARG, "unknown reduction");
     int rc;
     if ((rc = check_field(a, "a", false))) return rc;
-    bool two = op == IGG_RED_SUM_RATIO || op == IGG_RED_HALF_SQDIFF || op == IGG_RED_DOT ||
-               op == IGG_RED_MAX_ABS_DIFF;
-    if (two) {
+    *two = op == IGG_RED_SUM_RATIO || op == IGG_RED_HALF_SQDIFF || op == IGG_RED_DOT || op == IGG_RED_MAX_ABS_DIFF;
+    if (*two) {
         if ((rc = check_field(b, "b", false))) return rc;
         for (int d = 0; d < 3; ++d)
             if (a->size[d] != b->size[d]) return fail(IGG_ERR_SIZE, "a and b differ in size");
         if (a->dtype != b->dtype) return fail(IGG_ERR_DTYPE, "a and b must share one dtype");
     }
+    return IGG_OK;
+}
+
+int igg_reduce(int op, const igg_field *a, const igg_field *b, double *out, void *stream)
+{
+    bool two = false;
+    int rc;
+    if ((rc = check_reduce(op, a, b, out, &two))) return rc;
     if ((rc = ensure_device())) return rc;
     return launch_reduce(op, *a, two ? b : nullptr, out, (hipStream_t)stream);
+}
+
+int igg_reduce_noalloc(int op, const igg_field *a, const igg_field *b, double *out_dev, void *stream)
+{
+    bool two = false;
+    int rc;
+    if ((rc = check_reduce(op, a, b, out_dev, &two))) return rc;
+    return launch_reduce_noalloc(op, *a, two ? b : nullptr, out_dev, (hipStream_t)stream);
 }
 
 int igg_timing_enable(int on)

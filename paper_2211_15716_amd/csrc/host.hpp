@@ -221,6 +221,11 @@ int launch_flux_inner(int dtype, const FluxArgs &a, const Box &b, hipStream_t s)
 
 
 int launch_reduce(int op, const igg_field &a, const igg_field *b, double *out, hipStream_t s);
+// The same reduction into *out_dev (device memory), with the partial results
+// in the library's static device array instead of the grid's buffers: no
+// allocation, no synchronisation.
+constexpr int IGG_MAX_DEVICES = 64;
+int launch_reduce_noalloc(int op, const igg_field &a, const igg_field *b, double *out_dev, hipStream_t s);
 
 // FP16 stochastic-rounding key of a (seed, counter) pair.
 uint32_t sr_key(uint64_t seed, uint64_t counter);

@@ -2,6 +2,9 @@
 // conservation and dot-product sums).  Values are widened to FP64 before
 // they are combined; rows are dealt to a fixed number of work-groups and
 // combined in a fixed tree, so a call's bits do not vary between runs.
+#include <mutex>
+#include <string>
+
 #include "host.hpp"
 
 namespace igg {
@@ -69,19 +72,23 @@ k_reduce(const S *__restrict__ a, const S *__restrict__ b, int op, int nx, int n
     if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
 
-__global__ void __launch_bounds__(RED_THREADS) k_reduce_final(int op, int n, double *__restrict__ part)
+// Combines the n partial results in `part` and writes the value to *result.
+__global__ void __launch_bounds__(RED_THREADS)
+k_reduce_final(int op, int n, const double *__restrict__ part, double *__restrict__ result)
 {
     __shared__ double sh[RED_THREADS];
     double acc = identity(op);
     for (int q = threadIdx.x; q < n; q += RED_THREADS) acc = combine(op, acc, part[q]);
     double v = block_combine(op, acc, sh);
-    if (threadIdx.x == 0) part[RED_BLOCKS] = v;
+    if (threadIdx.x == 0) *result = v;
 }
 
+// The two launches of a reduction: partial results of at most RED_BLOCKS
+// work-groups into part[0..blocks), then their combination into *result.
 template <typename S>
-static int run(int op, const igg_field &a, const igg_field *b, double *out, hipStream_t s)
+static int launch_two(int op, const igg_field &a, const igg_field *b, double *part, int part_cap, double *result,
+                      hipStream_t s)
 {
-    Grid &g = grid();
     const int nx = (int)a.size[0], ny = (int)a.size[1], nz = (int)a.size[2];
     const bool all = op == IGG_RED_MAX || op == IGG_RED_MIN;
     int i0 = all ? 0 : 1, i1 = all ? nx : nx - 1;
@@ -89,24 +96,76 @@ static int run(int op, const igg_field &a, const igg_field *b, double *out, hipS
     int k0 = all ? 0 : 1, k1 = all ? nz : nz - 1;
     int64_t rows = (int64_t)(j1 - j0) * (k1 - k0);
     int blocks = (int)(rows < RED_BLOCKS ? (rows < 1 ? 1 : rows) : RED_BLOCKS);
+    if (blocks > part_cap)
+        return fail(IGG_ERR_SIZE, "reduction needs " + std::to_string(blocks) + " partial results, the buffer holds " +
+                                      std::to_string(part_cap));
     hipLaunchKernelGGL(k_reduce<S>, dim3(blocks), dim3(RED_THREADS), 0, s, (const S *)a.data,
-                       b ? (const S *)b->data : (const S *)nullptr, op, nx, ny, i0, i1, j0, j1, k0, k1,
-                       g.red_part);
+                       b ? (const S *)b->data : (const S *)nullptr, op, nx, ny, i0, i1, j0, j1, k0, k1, part);
     IGG_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, s, op, blocks, g.red_part);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, s, op, blocks, (const double *)part, result);
     IGG_HIP(hipGetLastError());
+    return IGG_OK;
+}
+
+static int launch_typed(int op, const igg_field &a, const igg_field *b, double *part, int part_cap, double *result,
+                        hipStream_t s)
+{
+    if (b && b->dtype != a.dtype) return fail(IGG_ERR_DTYPE, "a and b must share one dtype");
+    if (a.dtype == IGG_F64) return launch_two<double>(op, a, b, part, part_cap, result, s);
+    if (a.dtype == IGG_F32) return launch_two<float>(op, a, b, part, part_cap, result, s);
+    return launch_two<_Float16>(op, a, b, part, part_cap, result, s);
+}
+
+int launch_reduce(int op, const igg_field &a, const igg_field *b, double *out, hipStream_t s)
+{
+    Grid &g = grid();
+    int rc;
+    if ((rc = launch_typed(op, a, b, g.red_part, RED_BLOCKS, g.red_part + RED_BLOCKS, s))) return rc;
     IGG_HIP(hipMemcpyAsync(g.red_host, g.red_part + RED_BLOCKS, sizeof(double), hipMemcpyDeviceToHost, s));
     IGG_HIP(hipStreamSynchronize(s));
     *out = g.red_host[0];
     return IGG_OK;
 }
 
-int launch_reduce(int op, const igg_field &a, const igg_field *b, double *out, hipStream_t s)
+// ----------------------------------------------------- without allocation
+// Partial results of igg_reduce_noalloc: one array of 1024 doubles (8 KiB)
+// per device, held until the process ends.  Every call writes the partial
+// results it reads before reading them (same stream), so nothing needs
+// clearing; calls that overlap in time on one device share the array and
+// race.  Host code never uses its name as an address (on the host it is
+// only a stand-in); it takes the device address that hipGetSymbolAddress
+// returns for the current device, once per device.
+constexpr int kNoallocScratch = 1024;
+static __device__ __align__(256) double scratch[kNoallocScratch];
+
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[IGG_MAX_DEVICES];
+
+// The device address of `scratch` on the current device (looked up on the
+// first call on that device).
+static int scratch_on_current_device(double **ptr)
 {
-    if (b && b->dtype != a.dtype) return fail(IGG_ERR_DTYPE, "a and b must share one dtype");
-    if (a.dtype == IGG_F64) return run<double>(op, a, b, out, s);
-    if (a.dtype == IGG_F32) return run<float>(op, a, b, out, s);
-    return run<_Float16>(op, a, b, out, s);
+    int dev = -1;
+    IGG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= IGG_MAX_DEVICES)
+        return fail(IGG_ERR_ARG, "device index " + std::to_string(dev) + " above the library's limit");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        IGG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(IGG_ERR_HIP, "hipGetSymbolAddress returned a null address for the reduction scratch");
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return IGG_OK;
+}
+
+int launch_reduce_noalloc(int op, const igg_field &a, const igg_field *b, double *out_dev, hipStream_t s)
+{
+    double *part = nullptr;
+    int rc;
+    if ((rc = scratch_on_current_device(&part))) return rc;
+    return launch_typed(op, a, b, part, kNoallocScratch, out_dev, s);
 }
 
 }  // namespace igg

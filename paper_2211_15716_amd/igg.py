@@ -36,7 +36,7 @@ EXPORTS = ["igg_init_global_grid", "igg_global_size", "igg_topology", "igg_updat
            "igg_timing_enable", "igg_timing_read", "igg_last_error", "igg_version",
            "igg_nranks", "igg_rank_coords", "igg_neighbors", "igg_update_halo_ranks", "diffusion_step_ranks",
            "diffusion_step_adjoint_ranks", "diffusion_flux_step_ranks", "diffusion_flux_step_adjoint_ranks",
-           "diffusion_run", "igg_stream_probe"]
+           "diffusion_run", "igg_stream_probe", "igg_reduce_noalloc"]
 
 
 class IggError(RuntimeError):
@@ -93,6 +93,7 @@ def load():
     lib.diffusion_flux_step.argtypes = [_PF] * 6 + [d] * 5 + [_PI, vp]
     lib.diffusion_flux_step_adjoint.argtypes = [_PF] * 5 + [d] * 5 + [_PI, vp]
     lib.igg_reduce.argtypes = [ctypes.c_int, _PF, _PF, ctypes.POINTER(d), vp]
+    lib.igg_reduce_noalloc.argtypes = [ctypes.c_int, _PF, _PF, vp, vp]
     lib.igg_plan_split.argtypes = [_PI, _PI, (ctypes.c_int * 6) * 7, _PI]
     lib.igg_timing_enable.argtypes = [ctypes.c_int]
     lib.igg_timing_read.argtypes = [ctypes.POINTER(d), i64p, i64p, ctypes.POINTER(d)]
@@ -315,6 +316,18 @@ def reduce(op, a, b=None, stream=None):
     _check(load().igg_reduce(int(op), ctypes.byref(fa), ctypes.byref(fb) if fb is not None else None,
                              ctypes.byref(out), _stream(stream)))
     return out.value
+
+
+def reduce_noalloc(op, a, out, b=None, stream=None):
+    """reduce() into `out`, a one-element float64 device tensor, without
+    allocating and without synchronising (igg_reduce_noalloc)."""
+    import torch
+    if out.dtype != torch.float64 or out.numel() != 1 or not out.is_cuda:
+        raise ValueError("out must be a one-element float64 device tensor")
+    fa = field(a)
+    fb = field(b) if b is not None else None
+    _check(load().igg_reduce_noalloc(int(op), ctypes.byref(fa), ctypes.byref(fb) if fb is not None else None,
+                                     ctypes.c_void_p(out.data_ptr()), _stream(stream)))
 
 
 def plan_split(n, split):
