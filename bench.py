@@ -76,7 +76,11 @@ def parse():
     p.add_argument("--profile", action="store_true",
                    help="headline loop only, for running under rocprofv3")
     p.add_argument("--profile-adjoint", type=int, default=0, metavar="N",
-                   help="for rocprofv3 only: a 1 GiB reference copy, then 6 unsplit FP64 adjoint steps at N^3")
+                   help="for rocprofv3 only: the calibration stream, then 6 unsplit FP64 adjoint steps at N^3")
+    p.add_argument("--profile-flux", type=int, default=0, metavar="N",
+                   help="for rocprofv3 only: the calibration stream, then 6 FP32 flux-form steps at N^3")
+    p.add_argument("--profile-dtype", default="f64", choices=["f64", "f32", "f16"],
+                   help="with --profile: element type of the profiled steps (the headline fields rounded once)")
     p.add_argument("--split", default="16,2,2",
                    help="boundary widths of the timed steps, or 'none' for the unsplit schedule")
     return p.parse_args()
@@ -291,15 +295,23 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-def profile_adjoint(igg, torch, synth, n):
-    """The adjoint kernel alone, for HBM byte counters: a plain 1 GiB device
-    copy (the reference that scales the counters), then 6 unsplit FP64
-    adjoint steps on n^3 fields (uniform random lam', T_n, Ci; gCi from 0)."""
+def calibration_stream(igg, torch):
+    """A plain stream of known size ahead of the profiled kernels, the
+    reference that scales the HBM byte counters of a profiling run: the
+    streaming probe's 1R1W form on 2^27 doubles (1 GiB read, 1 GiB
+    written)."""
     src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
+    igg.stream_probe([src], [dst])
     torch.cuda.synchronize()
     del src, dst
+
+
+def profile_adjoint(igg, torch, synth, n):
+    """The adjoint kernel alone, for HBM byte counters: the calibration
+    stream, then 6 unsplit FP64 adjoint steps on n^3 fields (uniform random
+    lam', T_n, Ci; gCi from 0)."""
+    calibration_stream(igg, torch)
     igg.init_global_grid(n, n, n, dims=(1, 1, 1), periods=(1, 1, 1), overlaps=(2, 2, 2))
     lp, Tn, Ci = (torch.from_numpy(a).cuda() for a in synth.uniform_fields(n, n, n, seed=3, lo=0.5, hi=1.5, n=3))
     igg.update_halo(lp, Tn, Ci)
@@ -312,6 +324,50 @@ def profile_adjoint(igg, torch, synth, n):
     torch.cuda.synchronize()
     igg.finalize_global_grid()
     print(json.dumps({"profile_adjoint": n, "points_per_launch": (n - 2) ** 3, "bytes_per_point": 48}), flush=True)
+
+
+def profile_flux(igg, torch, synth, n):
+    """The fused flux-form pass alone, for HBM byte counters: the calibration
+    stream, then 6 unsplit FP32 flux-form steps on n^3 cells (the 768^3
+    recipe at edge n)."""
+    from paper_2211_15716_amd import diffusion
+    calibration_stream(igg, torch)
+    w = synth.workload("c5_768_flux", seed=0, n=n)
+    igg.init_global_grid(n, n, n, dims=(1, 1, 1), periods=(1, 1, 1), overlaps=(2, 2, 2))
+    T, C = diffusion.prepare_fields(w["T0"], w["Ci"], torch.float32)
+    d = (w["dx"], w["dy"], w["dz"])
+    dt = igg.diffusion_dt(C, w["lam"], *d)
+    prob = diffusion.FluxProblem(w["lam"], dt, *d)
+    diffusion.forward_with(prob, T, C, 6)
+    torch.cuda.synchronize()
+    igg.finalize_global_grid()
+    print(json.dumps({"profile_flux": n, "cells_per_launch": (n - 2) ** 3, "bytes_per_cell_fused": 24}), flush=True)
+
+
+def profile_step(igg, torch, synth, args):
+    """For rocprofv3 runs: the calibration stream, then the headline loop
+    alone (W warm-up and K timed steps of the 512^3 workload with its split,
+    the fields rounded once to --profile-dtype; FP16 stores rounded
+    stochastically as in the precision variant)."""
+    calibration_stream(igg, torch)
+    n = args.n
+    w = synth.workload("c2_512_fp64", seed=0, n=n)
+    d = (w["dx"], w["dy"], w["dz"])
+    tdt = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16}[args.profile_dtype]
+    igg.init_global_grid(n, n, n, dims=(1, 1, 1), periods=(1, 1, 1), overlaps=(2, 2, 2))
+    T = torch.from_numpy(w["T0"]).cuda().to(tdt).contiguous()
+    C = torch.from_numpy(w["Ci"]).cuda().to(tdt).contiguous()
+    del w
+    igg.update_halo(T, C)
+    dt = igg.diffusion_dt(C, 1.0, *d)
+    split = None if args.split == "none" else tuple(int(v) for v in args.split.split(","))
+    seed = 1234 if args.profile_dtype == "f16" else None
+    ms, _, k_ms, k_pts, _, _ = time_steps(igg, torch, T, T.clone(), C, 1.0, dt, *d, args.steps, args.warmup, split,
+                                          rnd_seed=seed)
+    igg.finalize_global_grid()
+    print(json.dumps({"profile": args.profile_dtype, "grid": [n, n, n], "split": args.split, "ms_per_step": ms,
+                      "kernel_ms": k_ms, "points_per_launch": k_pts, "bytes_per_point": 3 * T.element_size(),
+                      "kernel_source_hash": kernel_source_hash()}), flush=True)
 
 
 def main():
@@ -330,9 +386,18 @@ def main():
     if args.profile_adjoint:
         profile_adjoint(igg, torch, synth, args.profile_adjoint)
         return
+    if args.profile_flux:
+        profile_flux(igg, torch, synth, args.profile_flux)
+        return
+    if args.profile_dtype != "f64" and not args.profile:
+        raise SystemExit("--profile-dtype is for --profile runs only")
     torch.cuda.set_device(0)
     n = args.n
     K, Wm = args.steps, args.warmup
+
+    if args.profile:
+        profile_step(igg, torch, synth, args)
+        return
 
     # ---------------------------------------------------------------- headline FP64
     log(f"generating {n}^3 FP64 inputs (bump + lognormal Ci, seed 0)")
@@ -357,7 +422,7 @@ def main():
     k_bytes = 24.0 * k_pts
     k_gbs = k_bytes / (k_ms * 1e-3) / 1e9
     khash = kernel_source_hash()
-    traffic = traffic_from_profiles(khash, "inner_step_f64_512")
+    traffic = traffic_from_profiles(khash, "step_f64_512")
     log(f"FP64: {ms:.4f} ms/step (median; first pass {ms1:.4f}), T_eff {teff:.1f} GB/s; "
         f"step kernel {k_ms:.4f} ms, {k_gbs:.1f} GB/s")
 
@@ -385,16 +450,6 @@ def main():
         "ms_per_step_with_kernel_events": round(ms_inst, 5),
     }
 
-    if args.profile:
-        # a plain device copy of known size (1 GiB read, 1 GiB written), the
-        # reference that scales the HBM byte counters of a profiling run
-        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps(result), flush=True)
-        igg.finalize_global_grid()
-        return
 
     # ---------------------------------------------------------------- streaming ceiling of the mixes
     result["stream_ceiling_GBs"] = stream_ceilings(igg, torch)
