@@ -374,7 +374,9 @@ static bool vec2_ok(const AdjArgs &a)
 
 // 1 KB tile rows of 4 rows, 256 threads, one row per thread (the two
 // staged fields need many registers), 16-byte loads: FP64 128 points per
-// row (10% faster than 512-byte rows of 16 at 256^3 and 512^3 on MI355X),
+// row (10% faster than 512-byte rows of 16 at 256^3 and 512^3 on MI355X;
+// tiles of 8 or 16 such rows, with fewer y-halo rows to read, were 2-3%
+// slower, and two rows per thread need 206 registers),
 // FP32 256 points (24% faster than 8-byte loads on 512-byte rows at 512^3
 // and 768^3).  Narrower vectors, then one point per lane, where the row
 // length or alignment does not allow 16-byte loads.  The FP64 kernel is

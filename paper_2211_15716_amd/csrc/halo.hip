@@ -160,6 +160,63 @@ int launch_unpack_self(const igg_field &f, const SlabPack &pk, hipStream_t s)
     return IGG_OK;
 }
 
+// Gather form of the y and z halo update for a rank that is its own
+// neighbour: plane q of the four (y side 0: j = ny-1, side 1: j = 0; z
+// likewise) is filled point by point from the image of each point, the
+// index map img(0) = n-ol, img(n-1) = ol-1, img(c) = c otherwise, applied in
+// every dimension.  Images are inner points, which the step wrote, so the
+// four planes are independent and one launch fills them.
+struct SelfHalo {
+    unsigned char *base;
+    int nx, ny, nz;
+    int ol[3];
+    int esz;
+};
+
+__device__ __forceinline__ int self_img(int c, int n, int ol) { return c == 0 ? n - ol : (c == n - 1 ? ol - 1 : c); }
+
+template <typename E>
+__global__ void __launch_bounds__(256) k_halo_gather_yz(SelfHalo h)
+{
+    E *A = reinterpret_cast<E *>(h.base);
+    const int q = blockIdx.y;  // 0, 1: y planes (ny-1, 0); 2, 3: z planes (nz-1, 0)
+    const int64_t nx = h.nx, sxy = (int64_t)h.nx * h.ny;
+    const int nb = q < 2 ? h.nz : h.ny;
+    const int64_t count = nx * nb;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int a = (int)(e % nx), b = (int)(e / nx);
+        const int sa = self_img(a, h.nx, h.ol[0]);
+        int64_t dst, src;
+        if (q < 2) {
+            const int j = q == 0 ? h.ny - 1 : 0;
+            dst = (int64_t)b * sxy + (int64_t)j * nx + a;
+            src = (int64_t)self_img(b, h.nz, h.ol[2]) * sxy + (int64_t)self_img(j, h.ny, h.ol[1]) * nx + sa;
+        } else {
+            const int k = q == 2 ? h.nz - 1 : 0;
+            dst = (int64_t)k * sxy + (int64_t)b * nx + a;
+            src = (int64_t)self_img(k, h.nz, h.ol[2]) * sxy + (int64_t)self_img(b, h.ny, h.ol[1]) * nx + sa;
+        }
+        A[dst] = A[src];
+    }
+}
+
+int launch_halo_self_yz(const igg_field &f, hipStream_t s)
+{
+    Grid &g = grid();
+    SelfHalo h{(unsigned char *)f.data, (int)f.size[0], (int)f.size[1], (int)f.size[2], {0, 0, 0},
+               elem_bytes(f.dtype)};
+    for (int d = 0; d < 3; ++d) h.ol[d] = g.ol[d] + (int)(f.size[d] - g.n[d]);
+    const int64_t maxcount = (int64_t)h.nx * std::max(h.ny, h.nz);
+    const int64_t b = (maxcount + 255) / 256;
+    const dim3 grd((unsigned)std::min<int64_t>(std::max<int64_t>(b, 1), 1024), 4);
+    if (h.esz == 8) hipLaunchKernelGGL(k_halo_gather_yz<uint64_t>, grd, dim3(256), 0, s, h);
+    else if (h.esz == 4) hipLaunchKernelGGL(k_halo_gather_yz<uint32_t>, grd, dim3(256), 0, s, h);
+    else hipLaunchKernelGGL(k_halo_gather_yz<uint16_t>, grd, dim3(256), 0, s, h);
+    IGG_HIP(hipGetLastError());
+    return IGG_OK;
+}
+
 int launch_halo(const igg_field *fl, int nf, hipStream_t s, int dims)
 {
     Grid &g = grid();

@@ -174,6 +174,12 @@ int launch_step_slabs(int dtype, const StepArgs &a, const Split &sp, const SlabP
 // is copied into the halo plane of f it fills (y plane side 0 -> j = ny-1,
 // side 1 -> j = 0; z likewise), one launch for the four planes.
 int launch_unpack_self(const igg_field &f, const SlabPack &pk, hipStream_t s);
+// The y and z halo update of f for one rank that is its own neighbour in
+// every dimension, in one launch: every point of the y and z halo planes
+// takes the value of its image among the inner points, which is what the
+// dimension-ordered update leaves there (the x halo columns of inner rows
+// must already hold their images; the step kernels store them).
+int launch_halo_self_yz(const igg_field &f, hipStream_t s);
 // Send buffer of rank r, slot f (a field index of the halo update), side.
 unsigned char *halo_send_plane(int r, int f, int side);
 

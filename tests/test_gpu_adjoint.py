@@ -89,7 +89,9 @@ def test_adjoint_box_kernel_and_zmarch_paths_equal(n):
 def test_adjoint_schedules_and_x_exchange_forms_equal(monkeypatch):
     """The adjoint sweep under every schedule and both x-exchange forms (x
     halo of lam_n stored by the adjoint kernels, or a separate x pass) gives
-    the same loss and gradients, bit for bit, and matches the oracle."""
+    the same loss and gradients, bit for bit, and matches the oracle; the
+    one-launch form (schedule 3, where the kernel also stores the y and z
+    halo of lam_n) on the z-march and on the box kernels."""
     n = (70, 40, 36)
     nt = 6
     T0, Ci, Tobs = _fields(n, 58)
@@ -97,16 +99,17 @@ def test_adjoint_schedules_and_x_exchange_forms_equal(monkeypatch):
     dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
     L_ref, gT_ref, gC_ref = oracle.gradient(T0, Ci, Tobs, nt, 1.0, dt, dx, dx, dx)
     res = []
-    for sched in ("1", "0", "2"):
-        for xform in ("fused", "halo"):
-            monkeypatch.setenv("IGG_SCHEDULE", sched)
-            monkeypatch.setenv("IGG_X_EXCHANGE", xform)
-            with grid(n):
-                for split in [(16, 2, 2), None]:
-                    say("adjoint schedule", sched, xform, split)
-                    prob = diffusion.Problem(1.0, dt, dx, dx, dx, split=split)
-                    L, gT, gC, _ = diffusion.loss_and_grad(dev(T0), dev(Ci), dev(Tobs), prob, nt)
-                    res.append((L, host(gT), host(gC)))
+    combos = [(sched, xform, 0) for sched in ("1", "0", "2", "3") for xform in ("fused", "halo")]
+    combos.append(("3", "fused", None))  # the box kernels of small regions
+    for sched, xform, zmin in combos:
+        monkeypatch.setenv("IGG_SCHEDULE", sched)
+        monkeypatch.setenv("IGG_X_EXCHANGE", xform)
+        with grid(n, zmarch_min=zmin):
+            for split in [(16, 2, 2), None]:
+                say("adjoint schedule", sched, xform, zmin, split)
+                prob = diffusion.Problem(1.0, dt, dx, dx, dx, split=split)
+                L, gT, gC, _ = diffusion.loss_and_grad(dev(T0), dev(Ci), dev(Tobs), prob, nt)
+                res.append((L, host(gT), host(gC)))
     for L, gT, gC in res[1:]:
         assert L == res[0][0] and np.array_equal(gT, res[0][1]) and np.array_equal(gC, res[0][2])
     L, gT, gC = res[0]
