@@ -359,6 +359,26 @@ int diffusion_flux_step_adjoint_ranks(const igg_field *lam_n, const igg_field *l
  * IGG_ERR_DTYPE, IGG_ERR_HIP. */
 int igg_reduce(int op, const igg_field *a, const igg_field *b, double *out, void *stream);
 
+/* Seed of the adjoint sweep and restriction of a gradient to the unique
+ * points (the loss 0.5*||T_nt - T_obs||^2 over the inner points and its
+ * gradient lam = T_nt - T_obs, which lives on the inner points):
+ *   lam = T - T_obs on the inner points (T alone when T_obs is NULL, zero
+ *         when T is NULL too), zero on every halo point; then, with halo = 1,
+ *         the halo update of lam (periodic images; non-periodic halo planes
+ *         stay zero), as diffusion_step_adjoint expects of its input.
+ *   loss  nullable; needs T_obs: the FP64 loss, with the bits of igg_reduce
+ *         IGG_RED_HALF_SQDIFF on (T, T_obs); synchronises `stream`.
+ * T, T_obs and lam have the grid size and one element type (caller-owned);
+ * lam may not overlap T or T_obs.  One pass over the fields (and, with
+ * halo = 1, the halo launches).
+ * On a grid of virtual ranks each block is seeded alone (halo = 0) and one
+ * igg_update_halo_ranks follows.
+ * Errors: IGG_ERR_STATE (halo = 1 on a grid of virtual ranks), IGG_ERR_ARG
+ * (T_obs without T, loss without T_obs, halo not 0/1), IGG_ERR_SIZE,
+ * IGG_ERR_DTYPE, IGG_ERR_ALIAS, IGG_ERR_HIP. */
+int igg_adjoint_seed(const igg_field *T, const igg_field *T_obs, const igg_field *lam, int halo, double *loss,
+                     void *stream);
+
 /* igg_reduce for callers that cannot allocate device memory: code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
  * same reduction over the same points with the same kernels, so the same

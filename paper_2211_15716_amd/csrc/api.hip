@@ -1126,6 +1126,32 @@ int igg_reduce(int op, const igg_field *a, const igg_field *b, double *out, void
     return launch_reduce(op, *a, two ? b : nullptr, out, (hipStream_t)stream);
 }
 
+int igg_adjoint_seed(const igg_field *T, const igg_field *T_obs, const igg_field *lam, int halo, double *loss,
+                     void *stream)
+{
+    Grid &g = grid();
+    if (!g.init) return fail(IGG_ERR_STATE, "the global grid is not initialised");
+    int rc;
+    if ((rc = check_field(lam, "lam", true))) return rc;
+    if (T_obs && !T) return fail(IGG_ERR_ARG, "T_obs without T");
+    if (loss && !T_obs) return fail(IGG_ERR_ARG, "the loss needs T and T_obs");
+    if (halo != 0 && halo != 1) return fail(IGG_ERR_ARG, "halo must be 0 or 1");
+    if (halo && g.nranks > 1)
+        return fail(IGG_ERR_STATE, "the grid holds several virtual ranks: seed each block with halo = 0, then "
+                                   "igg_update_halo_ranks");
+    for (const igg_field *f : {T, T_obs}) {
+        if (!f) continue;
+        if ((rc = check_field(f, f == T ? "T" : "T_obs", true))) return rc;
+        if (f->dtype != lam->dtype) return fail(IGG_ERR_DTYPE, "T, T_obs and lam must share one dtype");
+        if (overlaps_mem(*f, *lam)) return fail(IGG_ERR_ALIAS, "lam shares memory with an input");
+    }
+    if ((rc = ensure_device())) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    if ((rc = launch_seed(T, T_obs, *lam, loss, s))) return rc;
+    if (halo && (rc = launch_halo(lam, 1, s))) return rc;
+    return loss ? read_reduce_result(loss, s) : IGG_OK;
+}
+
 int igg_reduce_noalloc(int op, const igg_field *a, const igg_field *b, double *out_dev, void *stream)
 {
     bool two = false;

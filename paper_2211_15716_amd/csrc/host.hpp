@@ -227,6 +227,11 @@ int launch_flux_inner(int dtype, const FluxArgs &a, const Box &b, hipStream_t s)
 
 
 int launch_reduce(int op, const igg_field &a, const igg_field *b, double *out, hipStream_t s);
+// lam = a - b (or a, or 0) on the inner points of lam, zero on its halo;
+// with loss, the FP64 loss 0.5*sum (a-b)^2 is left for read_reduce_result.
+int launch_seed(const igg_field *a, const igg_field *b, const igg_field &lam, double *loss, hipStream_t s);
+// The value the last reduction left on the device, after synchronising s.
+int read_reduce_result(double *out, hipStream_t s);
 // The same reduction into *out_dev (device memory), with the partial results
 // in the library's static device array instead of the grid's buffers: no
 // allocation, no synchronisation.

@@ -127,6 +127,98 @@ int launch_reduce(int op, const igg_field &a, const igg_field *b, double *out, h
     return IGG_OK;
 }
 
+// ------------------------------------------------------- adjoint seed
+// lam = a - b on the inner points (a alone without b, zero without a), zero
+// on every halo point; with want_loss, the partial sums of 0.5*(a-b)^2 for
+// k_reduce_final.  The inner rows are dealt to work-groups and walked by the
+// threads exactly as k_reduce walks them for IGG_RED_HALF_SQDIFF, so the
+// loss has the bits of that reduction.  The halo rows and columns are
+// zeroed in a second walk.
+template <typename S>
+__global__ void __launch_bounds__(RED_THREADS)
+k_seed(const S *__restrict__ a, const S *__restrict__ b, S *__restrict__ lam, int nx, int ny, int nz,
+       double *__restrict__ part)
+{
+    using C = compute_t<S>;
+    __shared__ double sh[RED_THREADS];
+    double acc = 0.0;
+    const int64_t h = ny - 2;
+    const int64_t rows = h * (nz - 2);
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+        const int j = 1 + (int)(r % h), k = 1 + (int)(r / h);
+        const int64_t base = (int64_t)k * nx * ny + (int64_t)j * nx;
+        for (int i = 1 + threadIdx.x; i < nx - 1; i += RED_THREADS) {
+            const int64_t p = base + i;
+            S v = S(0);
+            if (a) {
+                if (b) {
+                    v = (S)((C)a[p] - (C)b[p]);
+                    const double d = (double)(C)a[p] - (double)(C)b[p];
+                    acc += 0.5 * (d * d);
+                } else {
+                    v = a[p];
+                }
+            }
+            lam[p] = v;
+        }
+        if (threadIdx.x == 0) lam[base] = S(0);
+        if (threadIdx.x == 1) lam[base + nx - 1] = S(0);
+    }
+    // halo rows: j = 0 and ny-1 of every plane, then every row of planes 0 and nz-1
+    const int64_t hrows = 2 * (int64_t)nz + 2 * (int64_t)(ny - 2);
+    for (int64_t r = blockIdx.x; r < hrows; r += gridDim.x) {
+        int j, k;
+        if (r < 2 * (int64_t)nz) {
+            j = (r & 1) ? ny - 1 : 0;
+            k = (int)(r >> 1);
+        } else {
+            const int64_t q = r - 2 * (int64_t)nz;
+            j = 1 + (int)(q >> 1);
+            k = (q & 1) ? nz - 1 : 0;
+        }
+        const int64_t base = (int64_t)k * nx * ny + (int64_t)j * nx;
+        for (int i = threadIdx.x; i < nx; i += RED_THREADS) lam[base + i] = S(0);
+    }
+    if (part) {
+        double v = block_combine(IGG_RED_HALF_SQDIFF, acc, sh);
+        if (threadIdx.x == 0) part[blockIdx.x] = v;
+    }
+}
+
+int launch_seed(const igg_field *a, const igg_field *b, const igg_field &lam, double *loss, hipStream_t s)
+{
+    Grid &g = grid();
+    const int nx = (int)lam.size[0], ny = (int)lam.size[1], nz = (int)lam.size[2];
+    const int64_t rows = (int64_t)(ny - 2) * (nz - 2);
+    const int blocks = (int)(rows < RED_BLOCKS ? (rows < 1 ? 1 : rows) : RED_BLOCKS);
+    double *part = loss ? g.red_part : nullptr;
+    if (lam.dtype == IGG_F64)
+        hipLaunchKernelGGL(k_seed<double>, dim3(blocks), dim3(RED_THREADS), 0, s, a ? (const double *)a->data : nullptr,
+                           b ? (const double *)b->data : nullptr, (double *)lam.data, nx, ny, nz, part);
+    else if (lam.dtype == IGG_F32)
+        hipLaunchKernelGGL(k_seed<float>, dim3(blocks), dim3(RED_THREADS), 0, s, a ? (const float *)a->data : nullptr,
+                           b ? (const float *)b->data : nullptr, (float *)lam.data, nx, ny, nz, part);
+    else
+        hipLaunchKernelGGL(k_seed<_Float16>, dim3(blocks), dim3(RED_THREADS), 0, s,
+                           a ? (const _Float16 *)a->data : nullptr, b ? (const _Float16 *)b->data : nullptr,
+                           (_Float16 *)lam.data, nx, ny, nz, part);
+    IGG_HIP(hipGetLastError());
+    if (!loss) return IGG_OK;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, s, (int)IGG_RED_HALF_SQDIFF, blocks,
+                       (const double *)g.red_part, g.red_part + RED_BLOCKS);
+    IGG_HIP(hipGetLastError());
+    return IGG_OK;
+}
+
+int read_reduce_result(double *out, hipStream_t s)
+{
+    Grid &g = grid();
+    IGG_HIP(hipMemcpyAsync(g.red_host, g.red_part + RED_BLOCKS, sizeof(double), hipMemcpyDeviceToHost, s));
+    IGG_HIP(hipStreamSynchronize(s));
+    *out = g.red_host[0];
+    return IGG_OK;
+}
+
 // ----------------------------------------------------- without allocation
 // Partial results of igg_reduce_noalloc: one array of 1024 doubles (8 KiB)
 // per device, held until the process ends.  Every call writes the partial

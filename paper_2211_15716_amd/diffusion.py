@@ -163,21 +163,31 @@ def _clone(x):
 
 
 def _zeros_like(x):
-    return _map(torch.zeros_like, x)
+    """Zero-filled buffers like x (filled by the library)."""
+    def one(t):
+        y = torch.empty_like(t)
+        igg.adjoint_seed(y, halo=False)
+        return y
+    return _map(one, x)
+
+
+def _restrict(t, halo):
+    """A new buffer with t's inner points and a zero halo, then (halo set) the
+    halo update: the library's adjoint seed without T_obs."""
+    y = torch.empty_like(t)
+    igg.adjoint_seed(y, t, halo=halo)
+    return y
 
 
 def _fresh_like(x):
-    """New buffers like x holding only x's six halo faces: enough for a step's
-    output, since a step writes every inner point (and the halo planes of
-    periodic dimensions), and the halo planes of non-periodic dimensions are
-    the same in every state."""
-    def one(t):
-        y = torch.empty_like(t)
-        y[0], y[-1] = t[0], t[-1]
-        y[:, 0], y[:, -1] = t[:, 0], t[:, -1]
-        y[:, :, 0], y[:, :, -1] = t[:, :, 0], t[:, :, -1]
-        return y
-    return _map(one, x)
+    """New buffers for a step's output: a step writes every inner point and
+    the halo planes of periodic dimensions, so on a fully periodic grid an
+    uninitialised buffer will do; otherwise a copy of x carries the halo
+    planes of the non-periodic dimensions, which are the same in every
+    state."""
+    if all(igg.topology()["periods"]):
+        return _map(torch.empty_like, x)
+    return _clone(x)
 
 
 def _copy_(dst, src):
@@ -306,9 +316,8 @@ def _split_ops(ops):
 
 
 def _inner_only(t):
-    out = torch.zeros_like(t)
-    out[1:-1, 1:-1, 1:-1] = t[1:-1, 1:-1, 1:-1]
-    return out
+    """t's inner points with a zero halo (by the library)."""
+    return _restrict(t.contiguous(), False)
 
 
 class DiffusionSolve(torch.autograd.Function):
@@ -335,8 +344,7 @@ class DiffusionSolve(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         sweep = ctx.sweep
-        lam_nt = _inner_only(g.contiguous())
-        igg.update_halo(lam_nt)
+        lam_nt = _restrict(g.contiguous(), True)
         gT0, gCi = sweep.reverse(lam_nt)
         ctx.sweep = None
         return _inner_only(gT0), _inner_only(gCi), None, None, None
@@ -376,7 +384,7 @@ class DiffusionSolveRanks(torch.autograd.Function):
     @staticmethod
     def backward(ctx, *gs):
         sweep = ctx.sweep
-        lam_nt = [_inner_only(g.contiguous()) for g in gs]
+        lam_nt = [_restrict(g.contiguous(), False) for g in gs]
         igg.update_halo_ranks(*[(t,) for t in lam_nt])
         gT0, gCi = sweep.reverse(lam_nt)
         ctx.sweep = None
@@ -390,9 +398,10 @@ def loss_and_grad(T0, Ci, T_obs, prob, nt, schedule=("store_all",)):
     ops = checkpoint.make(schedule[0], nt, schedule[1] if len(schedule) > 1 else None)
     sweep = Sweep(prob, Ci, T0, ops)
     Tnt = sweep.forward(nt)
-    L = igg.reduce(igg.RED_HALF_SQDIFF, Tnt, T_obs)
-    lam_nt = _inner_only(Tnt - T_obs)
-    igg.update_halo(lam_nt)
+    # the seed lam_nt = T_nt - T_obs (inner points, halo updated) and the loss
+    # in one library call
+    lam_nt = torch.empty_like(Tnt)
+    L = igg.adjoint_seed(lam_nt, Tnt, T_obs, halo=True, loss=True)
     gT0, gCi = sweep.reverse(lam_nt)
     return L, _inner_only(gT0), _inner_only(gCi), sweep
 
@@ -407,8 +416,8 @@ def loss_and_grad_ranks(T0s, Cis, T_obs_s, prob, nt, schedule=("store_all",)):
     ops = checkpoint.make(schedule[0], nt, schedule[1] if len(schedule) > 1 else None)
     sweep = Sweep(prob, Cis, T0s, ops)
     Tnt = sweep.forward(nt)
-    L = sum(igg.reduce(igg.RED_HALF_SQDIFF, a, b) for a, b in zip(Tnt, T_obs_s))
-    lam_nt = [_inner_only(a - b) for a, b in zip(Tnt, T_obs_s)]
+    lam_nt = [torch.empty_like(a) for a in Tnt]
+    L = sum(igg.adjoint_seed(lt, a, b, halo=False, loss=True) for lt, a, b in zip(lam_nt, Tnt, T_obs_s))
     igg.update_halo_ranks(*[(t,) for t in lam_nt])
     gT0, gCi = sweep.reverse(lam_nt)
     return L, [_inner_only(t) for t in gT0], [_inner_only(t) for t in gCi], sweep

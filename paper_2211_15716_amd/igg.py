@@ -36,7 +36,7 @@ EXPORTS = ["igg_init_global_grid", "igg_global_size", "igg_topology", "igg_updat
            "igg_timing_enable", "igg_timing_read", "igg_last_error", "igg_version",
            "igg_nranks", "igg_rank_coords", "igg_neighbors", "igg_update_halo_ranks", "diffusion_step_ranks",
            "diffusion_step_adjoint_ranks", "diffusion_flux_step_ranks", "diffusion_flux_step_adjoint_ranks",
-           "diffusion_run", "igg_stream_probe", "igg_reduce_noalloc"]
+           "diffusion_run", "igg_stream_probe", "igg_reduce_noalloc", "igg_adjoint_seed"]
 
 
 class IggError(RuntimeError):
@@ -94,6 +94,7 @@ def load():
     lib.diffusion_flux_step_adjoint.argtypes = [_PF] * 5 + [d] * 5 + [_PI, vp]
     lib.igg_reduce.argtypes = [ctypes.c_int, _PF, _PF, ctypes.POINTER(d), vp]
     lib.igg_reduce_noalloc.argtypes = [ctypes.c_int, _PF, _PF, vp, vp]
+    lib.igg_adjoint_seed.argtypes = [_PF, _PF, _PF, ctypes.c_int, ctypes.POINTER(d), vp]
     lib.igg_plan_split.argtypes = [_PI, _PI, (ctypes.c_int * 6) * 7, _PI]
     lib.igg_timing_enable.argtypes = [ctypes.c_int]
     lib.igg_timing_read.argtypes = [ctypes.POINTER(d), i64p, i64p, ctypes.POINTER(d)]
@@ -316,6 +317,21 @@ def reduce(op, a, b=None, stream=None):
     _check(load().igg_reduce(int(op), ctypes.byref(fa), ctypes.byref(fb) if fb is not None else None,
                              ctypes.byref(out), _stream(stream)))
     return out.value
+
+
+def adjoint_seed(lam, T=None, T_obs=None, halo=True, loss=False, stream=None):
+    """lam = T - T_obs on the inner points (T alone without T_obs, zero
+    without T), zero halo, then the halo update when halo is set; returns the
+    FP64 loss 0.5*||T - T_obs||^2 over the inner points when loss is set
+    (needs T_obs; synchronises), else None."""
+    fl = field(lam)
+    ft = field(T) if T is not None else None
+    fo = field(T_obs) if T_obs is not None else None
+    out = ctypes.c_double()
+    _check(load().igg_adjoint_seed(ctypes.byref(ft) if ft is not None else None,
+                                   ctypes.byref(fo) if fo is not None else None, ctypes.byref(fl),
+                                   1 if halo else 0, ctypes.byref(out) if loss else None, _stream(stream)))
+    return out.value if loss else None
 
 
 def reduce_noalloc(op, a, out, b=None, stream=None):

@@ -168,7 +168,7 @@ def test_sweep_executes_schedule_on_buffers(sched, nt):
     prob = _RecordingProblem(T0)
     ops = ck.make(sched[0], nt, sched[1] if len(sched) > 1 else None)
     made = []
-    real_clone, real_fresh = diffusion._clone, diffusion._fresh_like
+    real = diffusion._clone, diffusion._fresh_like, diffusion._zeros_like
 
     def counting(f):
         def g(x):
@@ -177,14 +177,19 @@ def test_sweep_executes_schedule_on_buffers(sched, nt):
             return y
         return g
 
-    diffusion._clone, diffusion._fresh_like = counting(real_clone), counting(real_fresh)
+    # on CPU tensors the library's fills are replaced by torch's: a fresh
+    # buffer is a copy (it must carry the non-periodic halo planes) and the
+    # reverse sweep's zeroed buffers are torch zeros
+    diffusion._clone = counting(real[0])
+    diffusion._fresh_like = counting(real[0])
+    diffusion._zeros_like = lambda x: diffusion._map(torch.zeros_like, x)
     try:
         sw = diffusion.Sweep(prob, Ci, T0, ops)
         out = sw.forward(nt)
         assert torch.equal(out, states[nt])
         sw.reverse(torch.zeros_like(T0))
     finally:
-        diffusion._clone, diffusion._fresh_like = real_clone, real_fresh
+        diffusion._clone, diffusion._fresh_like, diffusion._zeros_like = real
     assert torch.equal(T0, T0_copy)
     assert len(prob.seen) == nt
     for q, seen in enumerate(prob.seen):

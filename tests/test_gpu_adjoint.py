@@ -326,3 +326,37 @@ def test_flux_form_checkpointed_adjoint_matches_oracle():
     assert abs(L0 - L_ref) <= 1e-12 * L_ref
     assert np.max(np.abs(inner(gT0) - inner(gT_ref))) <= 1e-12 * np.max(np.abs(inner(gT_ref)))
     assert np.max(np.abs(inner(gC0) - inner(gC_ref))) <= 1e-12 * np.max(np.abs(inner(gC_ref)))
+
+
+@pytest.mark.parametrize("periods", [(1, 1, 1), (1, 0, 1)])
+def test_adjoint_seed_and_restriction(periods):
+    """igg_adjoint_seed: lam = T - T_obs on the inner points with the halo of
+    lam the periodic images (zero in non-periodic dimensions), the loss equal
+    to igg_reduce(HALF_SQDIFF) bit for bit and to the exactly rounded sum;
+    without T_obs it restricts T to the inner points, without T it zeroes."""
+    n = (70, 36, 30)
+    say("adjoint seed", periods)
+    T0, Tobs = synth.uniform_fields(*n, seed=59, lo=0.3, hi=0.9, n=2)
+    ref = np.zeros_like(T0)
+    inner(ref)[...] = inner(T0) - inner(Tobs)
+    oracle.halo(ref, (2, 2, 2), periods)
+    L_exact = 0.5 * math.fsum((inner(T0) - inner(Tobs)).ravel() ** 2)
+    with grid(n, periods):
+        T, O = dev(T0), dev(Tobs)
+        lam = torch.full_like(T, 7.0)
+        L = igg.adjoint_seed(lam, T, O, halo=True, loss=True)
+        assert L == igg.reduce(igg.RED_HALF_SQDIFF, T, O)
+        assert abs(L - L_exact) <= 1e-13 * L_exact
+        assert np.array_equal(host(lam), ref)
+        r = torch.full_like(T, 7.0)
+        assert igg.adjoint_seed(r, T, halo=False) is None
+        want = np.zeros_like(T0)
+        inner(want)[...] = inner(T0)
+        assert np.array_equal(host(r), want)
+        z = torch.full_like(T, 7.0)
+        igg.adjoint_seed(z, halo=False)
+        assert not torch.any(z != 0).item()
+        with pytest.raises(igg.IggError):
+            igg.adjoint_seed(lam, None, O)
+        with pytest.raises(igg.IggError):
+            igg.adjoint_seed(T, T, O)  # lam aliases T
