@@ -13,10 +13,14 @@ SRC = os.path.join(HERE, "oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 
-def build(verbose=False):
+def build(verbose=False, sanitize=False):
+    """sanitize=True builds with AddressSanitizer and UndefinedBehaviorSanitizer
+    (load it with gcc's libasan preloaded, ASAN_OPTIONS=detect_leaks=0)."""
+    san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"] \
+        if sanitize else []
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
-           "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
-           "-o", LIB + ".tmp", SRC, "-lm"]
+           "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra"] + san + \
+          ["-o", LIB + ".tmp", SRC, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
@@ -25,4 +29,5 @@ def build(verbose=False):
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    import sys
+    print(build(verbose=True, sanitize="--sanitize" in sys.argv))

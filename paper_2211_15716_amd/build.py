@@ -30,9 +30,9 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src, verbose):
+def _compile(src, verbose, extra=()):
     obj = os.path.join(BUILD, os.path.basename(src)[:-4] + ".o")
-    cmd = [HIPCC] + CFLAGS + ["-c", src, "-o", obj]
+    cmd = [HIPCC] + CFLAGS + list(extra) + ["-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -43,14 +43,25 @@ def _compile(src, verbose):
     return obj
 
 
-def build(verbose=False, jobs=8):
+# Host-side sanitizers (a CPU check of the argument validation and host
+# logic): AddressSanitizer and UndefinedBehaviorSanitizer on the host pass
+# only; device code is built as usual.  Load such a build with clang's
+# ASan runtime preloaded (libclang_rt.asan-x86_64.so) and
+# ASAN_OPTIONS=detect_leaks=0.
+SANITIZE_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build(verbose=False, jobs=8, sanitize=False):
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
+    extra = SANITIZE_HOST if sanitize else []
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+        objs = list(ex.map(lambda s: _compile(s, verbose, extra), srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + \
-        ["-Wl,-rpath,/opt/rocm/lib", "-Wl,--no-undefined"]
+        ["-Wl,-rpath,/opt/rocm/lib", "-Wl,--no-undefined"] + \
+        (["-shared-libsan", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"] if sanitize else [])
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
@@ -59,4 +70,4 @@ def build(verbose=False, jobs=8):
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv))
