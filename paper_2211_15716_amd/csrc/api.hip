@@ -413,8 +413,9 @@ static int step_args(int r, const igg_field *T2, const igg_field *T, const igg_f
     // its copies in overlapping planes draw the same random bits)
     int per[3];
     for (int d = 0; d < 3; ++d) per[d] = g.periods[d] ? g.dims[d] * (g.n[d] - g.ol[d]) : 0;
+    const int gnx = g.dims[0] * (g.n[0] - g.ol[0]) + g.ol[0];
     const SrOrigin so{c[0] * (g.n[0] - g.ol[0]), c[1] * (g.n[1] - g.ol[1]), c[2] * (g.n[2] - g.ol[2]),
-                      g.dims[0] * (g.n[0] - g.ol[0]) + g.ol[0], per[0], per[1], per[2]};
+                      gnx, per[0], per[1], per[2], (gnx + 1) / 2};
     a = StepArgs{T2[r].data, T[r].data, Ci[r].data, g.n[0], g.n[1], g.n[2],
                  dt * lam, 1.0 / (dx * dx), 1.0 / (dy * dy), 1.0 / (dz * dz), key, stochastic, xh, so};
     return IGG_OK;

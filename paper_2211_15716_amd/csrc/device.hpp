@@ -96,6 +96,7 @@ __device__ __forceinline__ uint32_t point_bits(uint32_t pk, int i, int j, int nx
 struct SrOrigin {
     int ox, oy, oz, gnx;
     int px, py, pz;
+    int gnh;  // (gnx + 1) / 2: pairs of points per global row
 };
 
 __device__ __forceinline__ int sr_wrap(int g, int p) { return (p && g >= p) ? g - p : g; }
@@ -106,20 +107,51 @@ __device__ __forceinline__ uint32_t sr_plane_key(uint32_t key, int k, const SrOr
     return plane_key(key, sr_wrap(k + so.oz, so.pz));
 }
 
-// Random word of point (i, j) of a block's plane with key pk.
+// Random bits of point (i, j) of a block's plane with key pk.  One 32-bit
+// hash serves the two points 2m and 2m+1 of a global row (indices taken
+// modulo the period): the even point takes its low 16 bits, the odd point
+// its high 16 bits (FP16 stochastic rounding uses 13 of them in the normal
+// range, all 16 for subnormals).  A kernel holding both points of a pair
+// hashes once for the two (sr_point_bits2).
+__device__ __forceinline__ uint32_t sr_pair_word(uint32_t pk, int gi, int gj, const SrOrigin &so)
+{
+    return pcg_hash(pk ^ ((uint32_t)(gi >> 1) + (uint32_t)so.gnh * (uint32_t)gj));
+}
+
+__device__ __forceinline__ uint32_t sr_half(uint32_t w, int gi) { return (gi & 1) ? (w >> 16) : (w & 0xFFFFu); }
+
 __device__ __forceinline__ uint32_t sr_point_bits(uint32_t pk, int i, int j, const SrOrigin &so)
 {
-    return point_bits(pk, sr_wrap(i + so.ox, so.px), sr_wrap(j + so.oy, so.py), so.gnx);
+    const int gi = sr_wrap(i + so.ox, so.px);
+    return sr_half(sr_pair_word(pk, gi, sr_wrap(j + so.oy, so.py), so), gi);
+}
+
+// The bits of points (i, j) and (i+1, j): one hash when they are one pair
+// (even global index and no period wrap between them), else two.
+__device__ __forceinline__ void sr_point_bits2(uint32_t pk, int i, int j, const SrOrigin &so, uint32_t &r0,
+                                               uint32_t &r1)
+{
+    const int gi0 = sr_wrap(i + so.ox, so.px), gi1 = sr_wrap(i + 1 + so.ox, so.px);
+    const int gj = sr_wrap(j + so.oy, so.py);
+    const uint32_t w0 = sr_pair_word(pk, gi0, gj, so);
+    if ((gi0 & 1) == 0 && gi1 == gi0 + 1) {
+        r0 = w0 & 0xFFFFu;
+        r1 = w0 >> 16;
+    } else {
+        r0 = sr_half(w0, gi0);
+        r1 = sr_half(sr_pair_word(pk, gi1, gj, so), gi1);
+    }
 }
 
 // ---------------------------------------------------- FP16 stores
-// Unbiased stochastic rounding of a float to FP16: x is rounded up to the
-// next FP16 value with probability equal to its distance from the lower one
-// divided by their spacing.  In the FP16 normal range that is adding 13
-// uniform bits below the FP16 ulp to the magnitude and truncating (an FP16
-// value has 13 fewer fraction bits than a float); in the subnormal range the
-// spacing is 2^-24 and the comparison is done on the scaled value.  Values
-// already representable in FP16 are returned unchanged.
+// Unbiased stochastic rounding of a float to FP16 with 16 random bits r:
+// x is rounded up to the next FP16 value with probability equal to its
+// distance from the lower one divided by their spacing.  In the FP16 normal
+// range that is adding 13 uniform bits below the FP16 ulp to the magnitude
+// and truncating (an FP16 value has 13 fewer fraction bits than a float:
+// exact probabilities); in the subnormal range the spacing is 2^-24 and the
+// fraction is compared with a 16-bit uniform (probabilities to 2^-16).
+// Values already representable in FP16 are returned unchanged.
 __device__ __forceinline__ _Float16 round_sr(float x, uint32_t r)
 {
     float ax = __builtin_fabsf(x);
@@ -131,7 +163,7 @@ __device__ __forceinline__ _Float16 round_sr(float x, uint32_t r)
     }
     float s = ax * 16777216.0f;  // exact: multiples of 2^-24 become integers
     float f = __builtin_floorf(s);
-    float u = (float)(r >> 8) * (1.0f / 16777216.0f);
+    float u = (float)(r & 0xFFFFu) * (1.0f / 65536.0f);
     float m = (u < s - f) ? f + 1.0f : f;
     return (_Float16)__builtin_copysignf(m * 5.9604644775390625e-08f, x);
 }
@@ -142,6 +174,13 @@ template <typename S> struct Store {
 template <> struct Store<_Float16> {
     __device__ __forceinline__ static _Float16 put(float v, uint32_t r, int stochastic)
     {
+        // v is an FP32 value, rounded once to FP16 here.  The empty asm keeps
+        // the compiler from folding the conversion into the multiply-add that
+        // produced v (v_fma_mixlo/hi_f16 round the exact result to FP16 once,
+        // which can differ from rounding it to FP32 first): without it, some
+        // points of some kernels got the folded form and a point's bits
+        // depended on which kernel computed it.
+        __asm__("" : "+v"(v));
         return stochastic ? round_sr(v, r) : (_Float16)v;
     }
 };

@@ -19,6 +19,8 @@
 // rounding (SrOrigin).
 #include <stdlib.h>
 
+#include <type_traits>
+
 #include "host.hpp"
 
 namespace igg {
@@ -143,12 +145,15 @@ __device__ __forceinline__ void slab_put_row(S *row, int i, bool xin, bool full,
     }
 }
 
-// Wave w of the slab work (lane `lane`); waves past the end return.
-template <typename S, int VEC>
+// Wave w of the slab work (lane `lane`); waves past the end return.  SR:
+// stochastic rounding of FP16 stores (a template argument, so a kernel
+// without it carries none of its code).
+template <typename S, int VEC, int SR>
 __device__ __forceinline__ void slab_body(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__ Ci,
                                           const SlabSet &ss, compute_t<S> a, compute_t<S> rx, compute_t<S> ry,
-                                          compute_t<S> rz, uint32_t key, int stochastic, int64_t w, int lane)
+                                          compute_t<S> rz, uint32_t key, int64_t w, int lane)
 {
+    constexpr int stochastic = SR;
     using C = compute_t<S>;
     using V = typename VecOf<S, VEC>::type;
     constexpr int RUN = 64 * VEC;
@@ -220,6 +225,16 @@ __device__ __forceinline__ void slab_body(S *__restrict__ T2, const S *__restric
         if (lane == 63) fromhi = ec;
         const int jc = mz ? fixed : m, kc = mz ? m : fixed;
         const uint32_t pk = stochastic ? sr_plane_key(key, kc, ss.so) : 0u;
+        uint32_t rbits[VEC];
+        if constexpr (SR) {
+            if constexpr (VEC % 2 == 0) {
+#pragma unroll
+                for (int e = 0; e < VEC; e += 2) sr_point_bits2(pk, i + e, jc, ss.so, rbits[e], rbits[e + 1]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) rbits[e] = sr_point_bits(pk, i + e, jc, ss.so);
+            }
+        }
         V out;
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
@@ -231,8 +246,7 @@ __device__ __forceinline__ void slab_body(S *__restrict__ T2, const S *__restric
             const C ym = mz ? across_m : along_m, yp = mz ? across_p : along_p;
             const C zm = mz ? along_m : across_m, zp = mz ? along_p : across_p;
             const C v = diffuse<C>(c, xm, xp, ym, yp, zm, zp, widen<C>(lane_elem<S, VEC>(ci, e)), a, rx, ry, rz);
-            const uint32_t rb = stochastic ? sr_point_bits(pk, i + e, jc, ss.so) : 0u;
-            set_elem<S, VEC>(out, e, Store<S>::put(v, rb, stochastic));
+            set_elem<S, VEC>(out, e, Store<S>::put(v, stochastic ? rbits[e] : 0u, stochastic));
         }
         S *dst = T2 + p;
         if (full) {
@@ -284,13 +298,13 @@ __device__ __forceinline__ void slab_body(S *__restrict__ T2, const S *__restric
     }
 }
 
-template <typename S, int VEC>
+template <typename S, int VEC, int SR>
 __global__ void __launch_bounds__(256)
 k_step_slab(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__ Ci, SlabSet ss,
-            compute_t<S> a, compute_t<S> rx, compute_t<S> ry, compute_t<S> rz, uint32_t key, int stochastic)
+            compute_t<S> a, compute_t<S> rx, compute_t<S> ry, compute_t<S> rz, uint32_t key)
 {
-    slab_body<S, VEC>(T2, T, Ci, ss, a, rx, ry, rz, key, stochastic,
-                      (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), threadIdx.x & 63);
+    slab_body<S, VEC, SR>(T2, T, Ci, ss, a, rx, ry, rz, key,
+                          (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6), threadIdx.x & 63);
 }
 
 // --------------------------------------------------------------- z-march
@@ -328,12 +342,12 @@ struct ZTile {
 // Tile: TW = BX*VEC points by TH = TY*RY rows; the LDS plane tile adds one
 // halo row above and below (loaded by thread rows 0 and TY-1) and one halo
 // column left and right (loaded by lanes tx = 0 and BX-1).
-template <typename S, int VEC, int BX, int TY, int RY, int WRAP>
+template <typename S, int VEC, int BX, int TY, int RY, int WRAP, int SR>
 __global__ void __launch_bounds__(BX *TY)
 k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__ Ci, ZTile z,
-              compute_t<S> a, compute_t<S> rx, compute_t<S> ry, compute_t<S> rz, uint32_t key,
-              int stochastic)
+              compute_t<S> a, compute_t<S> rx, compute_t<S> ry, compute_t<S> rz, uint32_t key)
 {
+    constexpr int stochastic = SR;
     using C = compute_t<S>;
     using V = typename VecOf<S, VEC>::type;
     constexpr int TW = BX * VEC, TH = TY * RY, LH = TH + 2, LW = TW + 2;
@@ -343,8 +357,8 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
     int64_t g = blockIdx.x;
     if constexpr (!WRAP) {
         if (g < z.slab_blocks) {
-            slab_body<S, VEC>(T2, T, Ci, z.ss, a, rx, ry, rz, key, stochastic,
-                              g * (BX * TY / 64) + (int64_t)(threadIdx.x / 64), threadIdx.x & 63);
+            slab_body<S, VEC, SR>(T2, T, Ci, z.ss, a, rx, ry, rz, key,
+                                  g * (BX * TY / 64) + (int64_t)(threadIdx.x / 64), threadIdx.x & 63);
             return;
         }
     }
@@ -463,6 +477,24 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
         for (int r = 0; r < RY; ++r) {
             if (!crow[r]) continue;
             const int lr = 1 + ty * RY + r;
+            uint32_t rbits[VEC];
+            if constexpr (SR) {
+                if constexpr (!WRAP && VEC % 2 == 0) {
+#pragma unroll
+                    for (int q = 0; q < VEC; q += 2) sr_point_bits2(pk, i + q, jr[r], z.so, rbits[q], rbits[q + 1]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q) {
+                        int ir = i + q, jreal = jr[r];
+                        if (WRAP) {
+                            const bool left = ir < z.w2;
+                            ir = left ? ir + nx - z.w2 : ir - z.w2;
+                            jreal = left ? jreal - 1 : jreal;
+                        }
+                        rbits[q] = sr_point_bits(pk, ir, jreal, z.so);
+                    }
+                }
+            }
             V out;
 #pragma unroll
             for (int q = 0; q < VEC; ++q) {
@@ -475,14 +507,7 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
                 const C v = diffuse<C>(c, xm, xp, ym, yp, widen<C>(lane_elem<S, VEC>(tm[r], q)),
                                        widen<C>(lane_elem<S, VEC>(tp[r], q)), widen<C>(lane_elem<S, VEC>(ci[r], q)),
                                        a, rx, ry, rz);
-                int ir = i + q, jreal = jr[r];
-                if (WRAP) {
-                    const bool left = ir < z.w2;
-                    ir = left ? ir + nx - z.w2 : ir - z.w2;
-                    jreal = left ? jreal - 1 : jreal;
-                }
-                const uint32_t rb = stochastic ? sr_point_bits(pk, ir, jreal, z.so) : 0u;
-                set_elem<S, VEC>(out, q, Store<S>::put(v, rb, stochastic));
+                set_elem<S, VEC>(out, q, Store<S>::put(v, stochastic ? rbits[q] : 0u, stochastic));
             }
             S *dst = T2 + (int64_t)k * sxy + col[r];
             // dst + q is the point's own address; ix is its x index in the row
@@ -671,8 +696,17 @@ static int run_slabs(const StepArgs &a, const Box *b, int nb, const SlabPack *pk
     const SlabSet ss = make_slabset<S, VEC>(a, b, nb, pk);
     if (ss.waves == 0) return IGG_OK;
     const int64_t blocks = (ss.waves + 3) / 4;
-    hipLaunchKernelGGL((k_step_slab<S, VEC>), dim3((unsigned)blocks), dim3(256), 0, s, (S *)a.T2, (const S *)a.T,
-                       (const S *)a.Ci, ss, (C)a.a, (C)a.rx, (C)a.ry, (C)a.rz, a.key, a.stochastic);
+    bool sr_launched = false;
+    if constexpr (std::is_same<S, _Float16>::value) {
+        if (a.stochastic) {
+            hipLaunchKernelGGL((k_step_slab<S, VEC, 1>), dim3((unsigned)blocks), dim3(256), 0, s, (S *)a.T2,
+                               (const S *)a.T, (const S *)a.Ci, ss, (C)a.a, (C)a.rx, (C)a.ry, (C)a.rz, a.key);
+            sr_launched = true;
+        }
+    }
+    if (!sr_launched)
+        hipLaunchKernelGGL((k_step_slab<S, VEC, 0>), dim3((unsigned)blocks), dim3(256), 0, s, (S *)a.T2,
+                           (const S *)a.T, (const S *)a.Ci, ss, (C)a.a, (C)a.rx, (C)a.ry, (C)a.rz, a.key);
     IGG_HIP(hipGetLastError());
     return IGG_OK;
 }
@@ -723,9 +757,19 @@ static int run_zmarch(const StepArgs &a, const Box *b, int nbox, hipStream_t s, 
     if (blocks == 0) return IGG_OK;
     // a wrapped tile addresses its arrays from w2 points before each row
     const int64_t off = WRAP ? z.w2 : 0;
-    hipLaunchKernelGGL((k_step_zmarch<S, VEC, BX, TY, RY, WRAP>), dim3((unsigned)blocks), dim3(BX * TY), 0, s,
-                       (S *)a.T2 - off, (const S *)a.T - off, (const S *)a.Ci - off, z, (C)a.a, (C)a.rx, (C)a.ry,
-                       (C)a.rz, a.key, a.stochastic);
+    bool sr_launched = false;
+    if constexpr (std::is_same<S, _Float16>::value) {
+        if (a.stochastic) {
+            hipLaunchKernelGGL((k_step_zmarch<S, VEC, BX, TY, RY, WRAP, 1>), dim3((unsigned)blocks), dim3(BX * TY),
+                               0, s, (S *)a.T2 - off, (const S *)a.T - off, (const S *)a.Ci - off, z, (C)a.a,
+                               (C)a.rx, (C)a.ry, (C)a.rz, a.key);
+            sr_launched = true;
+        }
+    }
+    if (!sr_launched)
+        hipLaunchKernelGGL((k_step_zmarch<S, VEC, BX, TY, RY, WRAP, 0>), dim3((unsigned)blocks), dim3(BX * TY), 0,
+                           s, (S *)a.T2 - off, (const S *)a.T - off, (const S *)a.Ci - off, z, (C)a.a, (C)a.rx,
+                           (C)a.ry, (C)a.rz, a.key);
     IGG_HIP(hipGetLastError());
     return IGG_OK;
 }
