@@ -79,8 +79,9 @@ def parse():
                    help="for rocprofv3 only: the calibration stream, then 6 unsplit FP64 adjoint steps at N^3")
     p.add_argument("--profile-flux", type=int, default=0, metavar="N",
                    help="for rocprofv3 only: the calibration stream, then 6 FP32 flux-form steps at N^3")
-    p.add_argument("--profile-dtype", default="f64", choices=["f64", "f32", "f16"],
-                   help="with --profile: element type of the profiled steps (the headline fields rounded once)")
+    p.add_argument("--profile-dtype", default="f64", choices=["f64", "f32", "f16", "f16rn"],
+                   help="with --profile: element type of the profiled steps (the headline fields rounded once; "
+                        "f16 with stochastic rounding, f16rn with round-to-nearest stores)")
     p.add_argument("--split", default="16,2,2",
                    help="boundary widths of the timed steps, or 'none' for the unsplit schedule")
     return p.parse_args()
@@ -353,7 +354,7 @@ def profile_step(igg, torch, synth, args):
     n = args.n
     w = synth.workload("c2_512_fp64", seed=0, n=n)
     d = (w["dx"], w["dy"], w["dz"])
-    tdt = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16}[args.profile_dtype]
+    tdt = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16, "f16rn": torch.float16}[args.profile_dtype]
     igg.init_global_grid(n, n, n, dims=(1, 1, 1), periods=(1, 1, 1), overlaps=(2, 2, 2))
     T = torch.from_numpy(w["T0"]).cuda().to(tdt).contiguous()
     C = torch.from_numpy(w["Ci"]).cuda().to(tdt).contiguous()

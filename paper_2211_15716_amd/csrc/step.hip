@@ -603,13 +603,14 @@ struct ZLaunch {
     const char *remap_env;
     int64_t min_groups;
 };
-// FP64 inner region (and FP32 rows without vector loads): 16 planes, x-rows
+// FP64 inner region (and FP32 rows without vector loads): 8 planes, x-rows
 // of tiles dealt to the XCDs in turn; chunks halved below 4096 work-groups
 // (in a ping-pong time loop 4 planes beat 16 by 5% at 256^3 and by 6% at
-// 384^3).  At 512^3 8 planes make the unsplit kernel 2% faster but the
-// boundary-first step only 0.3%, so 16 keep the cost of the split low.
-static const ZLaunch kInner = {16, "IGG_ZCHUNK", 2, "IGG_XCD_REMAP", 4096};
+// 384^3; at 512^3 8 planes beat 16 by 1% in the one-launch step and by 2%
+// unsplit).
+static const ZLaunch kInner = {8, "IGG_ZCHUNK", 2, "IGG_XCD_REMAP", 4096};
 // FP32 inner region: 16 planes, contiguous ranges of tile rows per XCD
+// (at 512^3 the 32-row tiles take 8: 2048 work-groups)
 static const ZLaunch kInnerRanges = {16, "IGG_ZCHUNK", 3, "IGG_XCD_REMAP", 2048};
 // FP16 inner region: the same with chunks halved below 8192 work-groups (8
 // planes at 512^3: 1.5% faster than 16 in a ping-pong time loop)
@@ -784,10 +785,13 @@ static bool vec_ok(const StepArgs &a)
 }
 
 // Inner region.  FP64: 128-point (1 KB) tile rows, 16-byte loads, four
-// rows per thread, 16 rows per tile (two rows per thread below 2^26 points).  FP32: 256-point (1 KB) rows, 16-byte
-// loads, two rows per thread, 16 rows.  FP16: 256-point (512-byte) rows,
-// 8-byte loads, two rows per thread, 8 rows (256 threads: 1-3% faster than
-// 512-thread tiles of 16 rows at 256^3 and 512^3).
+// rows per thread, 16 rows per tile (two rows per thread below 2^26
+// points).  FP32: 256-point (1 KB) rows, 16-byte loads, two rows per
+// thread, 32 rows over 1024 threads from 2^26 points (16 rows below).
+// FP16: 256-point (512-byte) rows, 8-byte loads, two rows per thread, 8
+// rows (256 threads: 1-3% faster than 512-thread tiles of 16 rows at 256^3
+// and 512^3; 16-byte loads over 512-point rows, or four rows per thread,
+// 6-19% slower at 512^3: more registers, fewer waves).
 // These shapes and work-group mappings measured fastest on MI355X at 512^3.
 // Rows whose length does not allow vector loads take one point per lane;
 // regions below zmarch_min_points() take the box kernel.
@@ -836,7 +840,13 @@ int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s,
         return run_inner<double, 1, 64, 8, 2>(a, b, s, kInner, yz, nyz, pk);
     }
     if (dtype == IGG_F32) {
-        if (vec_ok<float, 4>(a)) return run_inner<float, 4, 64, 8, 2>(a, b, s, kInnerRanges, yz, nyz, pk);
+        if (vec_ok<float, 4>(a)) {
+            // 256 x 32 tiles over 1024 threads of 2 rows for regions of at
+            // least 2^26 points (4% faster than 256 x 16 tiles at 512^3)
+            if (box_count(b) >= ((int64_t)1 << 26))
+                return run_inner<float, 4, 64, 16, 2>(a, b, s, kInnerRanges, yz, nyz, pk);
+            return run_inner<float, 4, 64, 8, 2>(a, b, s, kInnerRanges, yz, nyz, pk);
+        }
         return run_inner<float, 1, 64, 8, 2>(a, b, s, kInner, yz, nyz, pk);
     }
     if (vec_ok<_Float16, 4>(a)) return run_inner<_Float16, 4, 64, 4, 2>(a, b, s, kInnerF16, yz, nyz, pk);
