@@ -80,12 +80,6 @@ __host__ __device__ __forceinline__ uint32_t pcg_hash(uint32_t v)
 // Key of one plane k for the key of a (seed, counter) pair.
 __device__ __forceinline__ uint32_t plane_key(uint32_t key, int k) { return pcg_hash(key + (uint32_t)k); }
 
-// Random word of point (i, j) in a plane with key pk.
-__device__ __forceinline__ uint32_t point_bits(uint32_t pk, int i, int j, int nx)
-{
-    return pcg_hash(pk ^ (uint32_t)(i + nx * j));
-}
-
 // Global origin of a block for the FP16 stochastic-rounding hash: the point
 // (i, j, k) of the block is hashed as (i + ox, j + oy, k + oz) in a global
 // index space gnx points wide, so every decomposition rounds a point alike.

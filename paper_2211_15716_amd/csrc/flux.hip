@@ -322,7 +322,9 @@ static int run_fused_zmarch(const FluxArgs &a, const Box &b, hipStream_t s)
     z.nty = (b.j1 - b.j0 + TH - 1) / TH;
     const int depth = b.k1 - b.k0;
     int zc = env_int_flux("IGG_FLUX_ZCHUNK", 0);
-    if (zc < 1) zc = zchunk_for_groups((int64_t)z.ntx * z.nty, depth, 16);
+    // chunks of 4 planes: at 768^3 (FP32) 9% faster than 16 and 4% faster
+    // than 8 (the two extra planes a chunk reads mostly hit in L2)
+    if (zc < 1) zc = zchunk_for_groups((int64_t)z.ntx * z.nty, depth, 4);
     z.zc = zc;
     z.remap = env_int_flux("IGG_FLUX_REMAP", 2);
     const int64_t blocks = (int64_t)z.ntx * z.nty * ((depth + zc - 1) / zc);
