@@ -805,8 +805,9 @@ static int run_inner(const StepArgs &a, const Box &b, hipStream_t s, const ZLaun
     // march chunks measured fastest for the launch at 512^3 (the slab waves
     // share it with the inner tiles, so their count matters less than the
     // rows each reloads per chunk): FP64 8 steps (0.5412 ms per step against
-    // 0.5459 with 2), FP32 2 (0.2930 against 0.3036 with 8), FP16 4
-    const int mc = sizeof(S) == 8 ? 8 : sizeof(S) == 4 ? 2 : 4;
+    // 0.5459 with 2), FP32 2 (0.2930 against 0.3036 with 8), FP16 4; FP64
+    // regions below 2^26 points take 2 (256^3: 72.8 us per step against 76.1)
+    const int mc = sizeof(S) == 8 ? (box_count(b) >= ((int64_t)1 << 26) ? 8 : 2) : sizeof(S) == 4 ? 2 : 4;
     const SlabSet ss = make_slabset<S, VEC>(a, yz, nyz, pk, mc);
     return run_zmarch<S, VEC, BX, TY, RY>(a, &b, 1, s, L, nullptr, &ss);
 }
