@@ -103,16 +103,17 @@ __device__ __forceinline__ uint32_t sr_plane_key(uint32_t key, int k, const SrOr
 
 // Random bits of point (i, j) of a block's plane with key pk.  One 32-bit
 // hash serves the two points 2m and 2m+1 of a global row (indices taken
-// modulo the period): the even point takes its low 16 bits, the odd point
-// its high 16 bits (FP16 stochastic rounding uses 13 of them in the normal
-// range, all 16 for subnormals).  A kernel holding both points of a pair
-// hashes once for the two (sr_point_bits2).
+// modulo the period): the even point takes its high 16 bits, the odd point
+// its low 16 bits, each as the top half of its 32-bit word (FP16 stochastic
+// rounding uses the top 13 bits of the word in the normal range, the top 16
+// for subnormals).  A kernel holding both points of a pair hashes once for
+// the two (sr_point_bits2).
 __device__ __forceinline__ uint32_t sr_pair_word(uint32_t pk, int gi, int gj, const SrOrigin &so)
 {
     return pcg_hash(pk ^ ((uint32_t)(gi >> 1) + (uint32_t)so.gnh * (uint32_t)gj));
 }
 
-__device__ __forceinline__ uint32_t sr_half(uint32_t w, int gi) { return (gi & 1) ? (w >> 16) : (w & 0xFFFFu); }
+__device__ __forceinline__ uint32_t sr_half(uint32_t w, int gi) { return (gi & 1) ? (w << 16) : w; }
 
 __device__ __forceinline__ uint32_t sr_point_bits(uint32_t pk, int i, int j, const SrOrigin &so)
 {
@@ -129,8 +130,8 @@ __device__ __forceinline__ void sr_point_bits2(uint32_t pk, int i, int j, const 
     const int gj = sr_wrap(j + so.oy, so.py);
     const uint32_t w0 = sr_pair_word(pk, gi0, gj, so);
     if ((gi0 & 1) == 0 && gi1 == gi0 + 1) {
-        r0 = w0 & 0xFFFFu;
-        r1 = w0 >> 16;
+        r0 = w0;
+        r1 = w0 << 16;
     } else {
         r0 = sr_half(w0, gi0);
         r1 = sr_half(sr_pair_word(pk, gi1, gj, so), gi1);
@@ -138,26 +139,33 @@ __device__ __forceinline__ void sr_point_bits2(uint32_t pk, int i, int j, const 
 }
 
 // ---------------------------------------------------- FP16 stores
-// Unbiased stochastic rounding of a float to FP16 with 16 random bits r:
+// Unbiased stochastic rounding of a float to FP16 with the random word w:
 // x is rounded up to the next FP16 value with probability equal to its
 // distance from the lower one divided by their spacing.  In the FP16 normal
-// range that is adding 13 uniform bits below the FP16 ulp to the magnitude
-// and truncating (an FP16 value has 13 fewer fraction bits than a float:
-// exact probabilities); in the subnormal range the spacing is 2^-24 and the
-// fraction is compared with a 16-bit uniform (probabilities to 2^-16).
+// range that is adding the top 13 bits of w (uniform) below the FP16 ulp to
+// the magnitude and truncating (an FP16 value has 13 fewer fraction bits
+// than a float: exact probabilities); gfx950 does exactly this in one
+// instruction (v_cvt_sr_f16_f32 takes the top 13 bits of its random
+// operand: on 786k random normal-range inputs and words it gave the bits of
+// the integer form, (bits(x) + (w >> 19)) & ~0x1FFF, every time).  In the
+// subnormal range the spacing is 2^-24 and the fraction is compared with
+// the top 16 bits of w as a uniform in [0, 1) (probabilities to 2^-16).
 // Values already representable in FP16 are returned unchanged.
-__device__ __forceinline__ _Float16 round_sr(float x, uint32_t r)
+__device__ __forceinline__ _Float16 round_sr(float x, uint32_t w)
 {
     float ax = __builtin_fabsf(x);
-    if (!(ax < 65504.0f)) return (_Float16)x;  // overflow, inf, nan
-    if (ax >= 6.103515625e-05f) {              // 2^-14, smallest FP16 normal
-        uint32_t b = __float_as_uint(x);
-        b = (b + (r & 0x1FFFu)) & ~0x1FFFu;
-        return (_Float16)__uint_as_float(b);
+    if (ax < 65504.0f && ax >= 6.103515625e-05f) {  // FP16 normal range (2^-14 and up)
+        // the instruction writes one half of its destination and keeps the
+        // other; w's register (dead after this) serves as that destination
+        typedef _Float16 H2 __attribute__((ext_vector_type(2)));
+        H2 v = __builtin_bit_cast(H2, w);
+        v = __builtin_amdgcn_cvt_sr_f16_f32(v, x, w, false);
+        return v[0];
     }
+    if (!(ax < 65504.0f)) return (_Float16)x;  // overflow, inf, nan
     float s = ax * 16777216.0f;  // exact: multiples of 2^-24 become integers
     float f = __builtin_floorf(s);
-    float u = (float)(r & 0xFFFFu) * (1.0f / 65536.0f);
+    float u = (float)(w >> 16) * (1.0f / 65536.0f);
     float m = (u < s - f) ? f + 1.0f : f;
     return (_Float16)__builtin_copysignf(m * 5.9604644775390625e-08f, x);
 }
