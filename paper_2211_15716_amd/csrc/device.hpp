@@ -146,8 +146,9 @@ __device__ __forceinline__ void sr_point_bits2(uint32_t pk, int i, int j, const 
 // the magnitude and truncating (an FP16 value has 13 fewer fraction bits
 // than a float: exact probabilities); gfx950 does exactly this in one
 // instruction (v_cvt_sr_f16_f32 takes the top 13 bits of its random
-// operand: on 786k random normal-range inputs and words it gave the bits of
-// the integer form, (bits(x) + (w >> 19)) & ~0x1FFF, every time).  In the
+// operand and gives the bits of the integer form, (bits(x) + (w >> 19)) &
+// ~0x1FFF: the GPU tests check every stored value of a step against that
+// form computed on the host).  In the
 // subnormal range the spacing is 2^-24 and the fraction is compared with
 // the top 16 bits of w as a uniform in [0, 1) (probabilities to 2^-16).
 // Values already representable in FP16 are returned unchanged.

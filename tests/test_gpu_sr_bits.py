@@ -1,0 +1,99 @@
+"""FP16 stochastic rounding bit for bit: every stored FP16 value of a step
+equals the rounding rule applied to the step's exact FP32 value with the
+random word of its point, both computed here on the host from their
+definitions: the PCG hash of Jarzynski & Olano (JCGT 2020) keyed on
+(seed, counter), plane and pair of points, and in the FP16 normal range
+truncation after adding the top 13 bits of the point's word below the FP16
+ulp.  This pins the hash scheme and the gfx950 conversion instruction the
+kernels use for it, in every kernel that stores FP16 points."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+from gpu_common import dev, grid, say  # noqa: E402
+from paper_2211_15716_amd import igg  # noqa: E402
+
+M32 = np.uint64(0xFFFFFFFF)
+
+
+def pcg_hash(v):
+    """PCG hash (one LCG step, then the RXS-M-XS output permutation) of
+    32-bit words, elementwise."""
+    v = np.asarray(v, dtype=np.uint64) & M32
+    state = (v * np.uint64(747796405) + np.uint64(2891336453)) & M32
+    word = (((state >> ((state >> np.uint64(28)) + np.uint64(4))) ^ state) * np.uint64(277803737)) & M32
+    return ((word >> np.uint64(22)) ^ word) & M32
+
+
+def sr_key(seed, counter):
+    """Key of a (seed, counter) pair: the hash chained over their four
+    32-bit halves."""
+    h = pcg_hash(counter >> 32)
+    h = pcg_hash(np.uint64(counter & 0xFFFFFFFF) ^ h)
+    h = pcg_hash(np.uint64(seed >> 32) ^ h)
+    return pcg_hash(np.uint64(seed & 0xFFFFFFFF) ^ h)
+
+
+def point_words(n, seed, counter, ol=2):
+    """The random word of every point (k, j, i) of one rank on a periodic
+    grid: plane key pcg(key + k), pair word pcg(plane key ^ (i // 2 + gnh *
+    j)) with indices taken modulo the period; even i takes the word, odd i
+    its low half moved to the top."""
+    nx, ny, nz = n
+    per = [d - ol for d in n]
+    wrap = lambda g, p: np.where(g >= p, g - p, g)  # noqa: E731
+    gi = wrap(np.arange(nx), per[0]).astype(np.uint64)
+    gj = wrap(np.arange(ny), per[1]).astype(np.uint64)
+    gk = wrap(np.arange(nz), per[2]).astype(np.uint64)
+    key = sr_key(seed, counter)
+    pk = pcg_hash((key + gk) & M32)
+    gnh = np.uint64((nx + 1) // 2)
+    pair = (gi[None, :] >> np.uint64(1)) + gnh * gj[:, None]
+    w = pcg_hash(pk[:, None, None] ^ (pair[None, :, :] & M32))
+    odd = (gi & np.uint64(1)).astype(bool)[None, None, :]
+    return np.where(odd, (w << np.uint64(16)) & M32, w)
+
+
+def round_rule(x32, w):
+    """FP16 bits of float32 values x32 in the FP16 normal range rounded with
+    words w: add the top 13 bits of w to the float's bits, clear the 13 bits
+    an FP16 value does not have."""
+    b = x32.view(np.uint32).astype(np.uint64)
+    y = ((b + (w >> np.uint64(19))) & np.uint64(0xFFFFE000)).astype(np.uint32).view(np.float32)
+    return y.astype(np.float16).view(np.uint16)
+
+
+@pytest.mark.parametrize("split,zmin", [(None, 0), ((16, 2, 2), 0), (None, None), ((16, 2, 2), None)])
+def test_fp16_stochastic_rounding_bits_match_their_definition(split, zmin):
+    """Unsplit and boundary-first steps, on the z-march tiles (with the slab
+    waves) and on the small-grid kernels."""
+    n = (70, 40, 36)
+    nx, ny, nz = n
+    seed, counter = 0x1234_5678_9ABC, 7
+    say("sr bits", split, zmin)
+    rng = np.random.default_rng(5)
+    T0 = 1.7 + 0.8 * rng.random((nz, ny, nx))
+    Ci = 0.25 + 0.5 * rng.random((nz, ny, nx))
+    dx = 1.0 / (nx - 1)
+    dt = dx * dx / 0.75 / 6.1
+    with grid(n, zmarch_min=zmin):
+        T16, C16 = dev(T0, torch.float16), dev(Ci, torch.float16)
+        exact = torch.empty(T16.shape, dtype=torch.float32, device="cuda")
+        igg.diffusion_step(exact, T16.float().contiguous(), C16.float().contiguous(), 1.0, dt, dx, dx, dx,
+                           split=split)
+        out = torch.empty_like(T16)
+        igg.diffusion_step(out, T16, C16, 1.0, dt, dx, dx, dx, split=split,
+                           rnd=igg.rounding("stochastic", seed, counter))
+        torch.cuda.synchronize()
+        x = exact.cpu().numpy()[1:-1, 1:-1, 1:-1]
+        got = out.cpu().numpy().view(np.uint16)[1:-1, 1:-1, 1:-1]
+    ax = np.abs(x)
+    assert np.all((ax >= 2.0 ** -14) & (ax < 65504.0))  # the normal range the rule covers
+    w = point_words(n, seed, counter)[1:-1, 1:-1, 1:-1]
+    want = round_rule(np.ascontiguousarray(x), w)
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, f"{len(bad)} points differ, first (k, j, i) {tuple(bad[0])}"
+    # and the rounding did something: both directions occur
+    rn = x.astype(np.float16).view(np.uint16)
+    assert np.any(got != rn)
