@@ -85,6 +85,33 @@ struct AdjTile {
     XHalo xh;
 };
 
+// Loads and stores of a whole vector type T at a byte offset from a buffer
+// descriptor's base (AUX = 2: non-temporal).
+template <typename T, int AUX>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    constexpr int B = sizeof(T);
+    if constexpr (B == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
+    else if constexpr (B == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, AUX));
+}
+template <typename T, int AUX>
+__device__ __forceinline__ void buf_store(const T &v, __amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    constexpr int B = sizeof(T);
+    using U8 = unsigned int __attribute__((ext_vector_type(2)));
+    using U16 = unsigned int __attribute__((ext_vector_type(4)));
+    if constexpr (B == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, AUX);
+    else if constexpr (B == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U8, v), r, off, 0, AUX);
+    else
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U16, v), r, off, 0, AUX);
+}
+
 template <typename C, int VEC> struct AVec {
     typedef C type __attribute__((ext_vector_type(VEC)));
 };
@@ -122,7 +149,9 @@ __device__ __forceinline__ void set_el(typename AVec<C, VEC>::type &v, int q, C 
 // tiling).  mu = Ci .* lp and T_n of plane k are staged in two
 // double-buffered LDS tiles; lp, mu and T_n of planes k-1..k+1 (k+2 in
 // flight) sit in registers.  gCi is read and written once per point and
-// lam_n written once: non-temporal.
+// lam_n written once: non-temporal.  The products mu of the planes in
+// flight are formed when the queue rotates, after the plane's arithmetic,
+// so the loads are not waited for inside the plane (256^3: 3.5% faster).
 template <typename C, int VEC, int BX, int TY, int RY, int FORM, int WAVES>
 __global__ void __launch_bounds__(BX *TY) __attribute__((amdgpu_waves_per_eu(WAVES)))
 k_adj_zmarch(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restrict__ Tn,
@@ -169,16 +198,25 @@ k_adj_zmarch(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restric
     const int xh = (tx == 0) ? x0 - 1 : x0 + TW;
     const int hcol = (tx == 0) ? 0 : LW - 1;
 
+    // loads through a buffer descriptor per array and plane (scalar
+    // registers) with 32-bit byte offsets in the plane (the launcher keeps
+    // planes below 2 GiB): no 64-bit address registers per lane, which
+    // leaves room under the 128-register cap for the deferred products below
+    const uint32_t pb = (uint32_t)(sxy * (int64_t)sizeof(C));
+    auto rs = [&](const C *A, int k) {
+        return __builtin_amdgcn_make_buffer_rsrc((void *)(A + (int64_t)k * sxy), 0, (int)pb, 0x00020000);
+    };
     auto ld = [&](const C *A, int k, int64_t c) -> V {
         V v{};
-        if (xin) v = *reinterpret_cast<const V *>(A + (int64_t)k * sxy + c);
+        if (xin) v = buf_load<V, 0>(rs(A, k), (uint32_t)(c * (int64_t)sizeof(C)));
         return v;
     };
     auto ld_nt = [&](const C *A, int k, int64_t c) -> V {
         V v{};
-        if (xin) v = __builtin_nontemporal_load(reinterpret_cast<const V *>(A + (int64_t)k * sxy + c));
+        if (xin) v = buf_load<V, 2>(rs(A, k), (uint32_t)(c * (int64_t)sizeof(C)));
         return v;
     };
+    auto lds1 = [&](const C *A, int k, int64_t c) -> C { return buf_load<C, 0>(rs(A, k), (uint32_t)(c * (int64_t)sizeof(C))); };
     auto mul = [](V x, V y) -> V {
         V out;
 #pragma unroll
@@ -199,9 +237,9 @@ k_adj_zmarch(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restric
         tc[r] = ld(Tn, kb, col[r]);
         tp[r] = ld(Tn, kb + 1, col[r]);
         gc[r] = crow[r] ? ld_nt(gCi, kb, col[r]) : V{};
-        const int64_t ph = (int64_t)kb * sxy + col[r] - i + xh;
-        hmu[r] = own_h ? Ci[ph] * lp[ph] : C(0);
-        hT[r] = own_h ? Tn[ph] : C(0);
+        const int64_t ph = col[r] - i + xh;
+        hmu[r] = own_h ? lds1(Ci, kb, ph) * lds1(lp, kb, ph) : C(0);
+        hT[r] = own_h ? lds1(Tn, kb, ph) : C(0);
     }
     V ymu = hy ? mul(ld(Ci, kb, colhy), ld(lp, kb, colhy)) : V{};
     V yT = hy ? ld(Tn, kb, colhy) : V{};
@@ -209,20 +247,24 @@ k_adj_zmarch(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restric
     for (int k = kb; k < ke; ++k) {
         const int buf = (k - kb) & 1;
         const bool more = k + 1 < ke;
-        V mn[RY], tn[RY], ln2[RY], gn[RY], ymu_n{}, yT_n{};
-        C hmu_n[RY], hT_n[RY];
+        // loads for the next planes, consumed one iteration later (Ci and
+        // lp raw: their products are formed at the rotation below)
+        V cn[RY], tn[RY], ln2[RY], gn[RY], yc_n{}, yl_n{}, yT_n{};
+        C hc_n[RY], hl_n[RY], hT_n[RY];
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             ln2[r] = more ? ld(lp, k + 2, col[r]) : V{};
-            mn[r] = more ? mul(ld(Ci, k + 2, col[r]), ln2[r]) : V{};
+            cn[r] = more ? ld(Ci, k + 2, col[r]) : V{};
             tn[r] = more ? ld(Tn, k + 2, col[r]) : V{};
             gn[r] = (more && crow[r]) ? ld_nt(gCi, k + 1, col[r]) : V{};
-            const int64_t ph = (int64_t)(k + 1) * sxy + col[r] - i + xh;
-            hmu_n[r] = (more && own_h) ? Ci[ph] * lp[ph] : C(0);
-            hT_n[r] = (more && own_h) ? Tn[ph] : C(0);
+            const int64_t ph = col[r] - i + xh;
+            hc_n[r] = (more && own_h) ? lds1(Ci, k + 1, ph) : C(0);
+            hl_n[r] = (more && own_h) ? lds1(lp, k + 1, ph) : C(0);
+            hT_n[r] = (more && own_h) ? lds1(Tn, k + 1, ph) : C(0);
         }
         if (more && hy) {
-            ymu_n = mul(ld(Ci, k + 1, colhy), ld(lp, k + 1, colhy));
+            yc_n = ld(Ci, k + 1, colhy);
+            yl_n = ld(lp, k + 1, colhy);
             yT_n = ld(Tn, k + 1, colhy);
         }
 #pragma unroll
@@ -272,8 +314,9 @@ k_adj_zmarch(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restric
             }
             const int64_t p = (int64_t)k * sxy + col[r];
             if (xin && i >= z.b.i0 && i + VEC <= z.b.i1) {
-                __builtin_nontemporal_store(lo, reinterpret_cast<V *>(lam_n + p));
-                __builtin_nontemporal_store(go, reinterpret_cast<V *>(gCi + p));
+                const uint32_t ob = (uint32_t)(col[r] * (int64_t)sizeof(C));
+                buf_store<V, 2>(lo, rs(lam_n, k), ob);
+                buf_store<V, 2>(go, rs(gCi, k), ob);
             } else if (xin) {
 #pragma unroll
                 for (int q = 0; q < VEC; ++q)
@@ -292,17 +335,17 @@ k_adj_zmarch(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restric
         for (int r = 0; r < RY; ++r) {
             mm[r] = mc[r];
             mc[r] = mp[r];
-            mp[r] = mn[r];
+            mp[r] = mul(cn[r], ln2[r]);
             lc[r] = lq[r];
             lq[r] = ln2[r];
             tm[r] = tc[r];
             tc[r] = tp[r];
             tp[r] = tn[r];
             gc[r] = gn[r];
-            hmu[r] = hmu_n[r];
+            hmu[r] = hc_n[r] * hl_n[r];
             hT[r] = hT_n[r];
         }
-        ymu = ymu_n;
+        ymu = mul(yc_n, yl_n);
         yT = yT_n;
     }
 }
@@ -402,7 +445,10 @@ static int adjoint_inner(int dtype, const AdjArgs &a, const Box &b, hipStream_t 
 
 int launch_adjoint_inner(int dtype, const AdjArgs &a, const Box &b, hipStream_t s)
 {
-    if (box_count(b) < zmarch_min_points()) return launch_adjoint_boxes(dtype, a, &b, 1, s);
+    // the z-march kernel addresses a plane with 32-bit offsets (2 GiB at most)
+    const int64_t plane = (int64_t)a.nx * a.ny * (dtype == IGG_F64 ? 8 : 4);
+    if (box_count(b) < zmarch_min_points() || plane >= ((int64_t)1 << 31))
+        return launch_adjoint_boxes(dtype, a, &b, 1, s);
     return a.form == 1 ? adjoint_inner<1>(dtype, a, b, s) : adjoint_inner<0>(dtype, a, b, s);
 }
 
