@@ -85,33 +85,6 @@ struct AdjTile {
     XHalo xh;
 };
 
-// Loads and stores of a whole vector type T at a byte offset from a buffer
-// descriptor's base (AUX = 2: non-temporal).
-template <typename T, int AUX>
-__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off)
-{
-    constexpr int B = sizeof(T);
-    if constexpr (B == 4)
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
-    else if constexpr (B == 8)
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
-    else
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, AUX));
-}
-template <typename T, int AUX>
-__device__ __forceinline__ void buf_store(const T &v, __amdgpu_buffer_rsrc_t r, uint32_t off)
-{
-    constexpr int B = sizeof(T);
-    using U8 = unsigned int __attribute__((ext_vector_type(2)));
-    using U16 = unsigned int __attribute__((ext_vector_type(4)));
-    if constexpr (B == 4)
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, AUX);
-    else if constexpr (B == 8)
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U8, v), r, off, 0, AUX);
-    else
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U16, v), r, off, 0, AUX);
-}
-
 template <typename C, int VEC> struct AVec {
     typedef C type __attribute__((ext_vector_type(VEC)));
 };
@@ -202,10 +175,8 @@ k_adj_zmarch(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restric
     // registers) with 32-bit byte offsets in the plane (the launcher keeps
     // planes below 2 GiB): no 64-bit address registers per lane, which
     // leaves room under the 128-register cap for the deferred products below
-    const uint32_t pb = (uint32_t)(sxy * (int64_t)sizeof(C));
-    auto rs = [&](const C *A, int k) {
-        return __builtin_amdgcn_make_buffer_rsrc((void *)(A + (int64_t)k * sxy), 0, (int)pb, 0x00020000);
-    };
+    const int64_t pb = sxy * (int64_t)sizeof(C);
+    auto rs = [&](const C *A, int k) { return buf_rsrc(A + (int64_t)k * sxy, pb); };
     auto ld = [&](const C *A, int k, int64_t c) -> V {
         V v{};
         if (xin) v = buf_load<V, 0>(rs(A, k), (uint32_t)(c * (int64_t)sizeof(C)));

@@ -188,6 +188,42 @@ template <> struct Store<_Float16> {
     }
 };
 
+// ------------------------------------------------------- buffer access
+// Loads and stores of a whole vector type T (4, 8 or 16 bytes) at a byte
+// offset from a buffer descriptor's base (AUX = 2: non-temporal).  A
+// descriptor per array and plane lives in scalar registers, so a kernel
+// addresses its lanes with 32-bit offsets instead of 64-bit pointers.
+template <typename T, int AUX>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    constexpr int B = sizeof(T);
+    if constexpr (B == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
+    else if constexpr (B == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, AUX));
+}
+template <typename T, int AUX>
+__device__ __forceinline__ void buf_store(const T &v, __amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    constexpr int B = sizeof(T);
+    using U8 = unsigned int __attribute__((ext_vector_type(2)));
+    using U16 = unsigned int __attribute__((ext_vector_type(4)));
+    if constexpr (B == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, AUX);
+    else if constexpr (B == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U8, v), r, off, 0, AUX);
+    else
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U16, v), r, off, 0, AUX);
+}
+
+// A descriptor for the bytes [p, p + bytes) (bytes below 2^31).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, int64_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, 0x00020000);
+}
+
 // ------------------------------------------------------------------ boxes
 // Half-open index box [i0,i1) x [j0,j1) x [k0,k1).
 struct Box {
