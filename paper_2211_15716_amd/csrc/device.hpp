@@ -189,7 +189,7 @@ template <> struct Store<_Float16> {
 };
 
 // ------------------------------------------------------- buffer access
-// Loads and stores of a whole vector type T (4, 8 or 16 bytes) at a byte
+// Loads and stores of a whole vector type T (2, 4, 8 or 16 bytes) at a byte
 // offset from a buffer descriptor's base (AUX = 2: non-temporal).  A
 // descriptor per array and plane lives in scalar registers, so a kernel
 // addresses its lanes with 32-bit offsets instead of 64-bit pointers.
@@ -197,7 +197,10 @@ template <typename T, int AUX>
 __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off)
 {
     constexpr int B = sizeof(T);
-    if constexpr (B == 4)
+    static_assert(B == 2 || B == 4 || B == 8 || B == 16, "buffer access of 2, 4, 8 or 16 bytes");
+    if constexpr (B == 2)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, AUX));
+    else if constexpr (B == 4)
         return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX));
     else if constexpr (B == 8)
         return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX));
@@ -208,9 +211,12 @@ template <typename T, int AUX>
 __device__ __forceinline__ void buf_store(const T &v, __amdgpu_buffer_rsrc_t r, uint32_t off)
 {
     constexpr int B = sizeof(T);
+    static_assert(B == 2 || B == 4 || B == 8 || B == 16, "buffer access of 2, 4, 8 or 16 bytes");
     using U8 = unsigned int __attribute__((ext_vector_type(2)));
     using U16 = unsigned int __attribute__((ext_vector_type(4)));
-    if constexpr (B == 4)
+    if constexpr (B == 2)
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, off, 0, AUX);
+    else if constexpr (B == 4)
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, off, 0, AUX);
     else if constexpr (B == 8)
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U8, v), r, off, 0, AUX);
