@@ -391,8 +391,9 @@ static bool vec2_ok(const AdjArgs &a)
 // 1 KB tile rows of 4 rows, 256 threads, one row per thread (the two
 // staged fields need many registers), 16-byte loads: FP64 128 points per
 // row (10% faster than 512-byte rows of 16 at 256^3 and 512^3 on MI355X;
-// tiles of 8 or 16 such rows, with fewer y-halo rows to read, were 2-3%
-// slower, and two rows per thread need 206 registers),
+// two rows per thread need 206 registers; since the products of the planes
+// in flight moved to the rotation, 16-row tiles of 1024 threads pay at
+// 512^3, see below),
 // FP32 256 points (24% faster than 8-byte loads on 512-byte rows at 512^3
 // and 768^3).  Narrower vectors, then one point per lane, where the row
 // length or alignment does not allow 16-byte loads.  The FP64 kernel is
@@ -406,8 +407,12 @@ static int adjoint_inner(int dtype, const AdjArgs &a, const Box &b, hipStream_t 
     {
         if (!vec2_ok<double>(a)) return run_zmarch<double, 1, 64, 8, 2, FORM>(a, b, s);
         const int waves = env_int("IGG_ADJ_WAVES", 4);
-        return waves == 4 ? run_zmarch<double, 2, 64, 4, 1, FORM, 4>(a, b, s)
-                          : run_zmarch<double, 2, 64, 4, 1, FORM>(a, b, s);
+        if (waves != 4) return run_zmarch<double, 2, 64, 4, 1, FORM>(a, b, s);
+        // regions of 2^26 points and more: 16-row tiles over 1024 threads
+        // (512^3: 4-10% faster than 4 rows on three boxes; 384^3 and 256^3
+        // keep 4 rows, equal or faster there)
+        if (box_count(b) >= ((int64_t)1 << 26)) return run_zmarch<double, 2, 64, 16, 1, FORM, 4>(a, b, s);
+        return run_zmarch<double, 2, 64, 4, 1, FORM, 4>(a, b, s);
     }
     if (vec2_ok<float, 4>(a)) return run_zmarch<float, 4, 64, 4, 1, FORM>(a, b, s);
     return vec2_ok<float>(a) ? run_zmarch<float, 2, 64, 8, 1, FORM>(a, b, s)

@@ -4,7 +4,8 @@ configurations bench.py times: every unique point of the 512^3 FP64 run
 forms against the FP64 oracle run, the 256^3 inverse-problem gradients
 (nt = 200, snapshots every 16) against the oracle's adjoint sweep, and the
 staggered flux form against the oracle's flux loop on a multi-tile grid and
-at 768^3 on light-cone samples.
+at 768^3 on light-cone samples, and one adjoint step (both forms) on a region
+above 2^26 points, where the adjoint kernel takes its 1024-thread tiles.
 
 The inputs are the seeded workload recipes; every expected value comes from
 the oracle."""
@@ -162,3 +163,42 @@ def test_c5_768_flux_form_samples_match_oracle():
     e32 = np.max(np.abs(got["f32"] - ref)) / np.max(np.abs(ref))
     say("c5 errors", e64, e32)
     assert e64 <= 1e-12 and e32 <= 1e-5
+
+
+@pytest.mark.parametrize("form", ["laplacian", "flux"])
+def test_adjoint_step_large_region_matches_oracle(form):
+    """One adjoint step on a region of more than 2^26 points (the FP64
+    kernel's 16-row tiles of 1024 threads, as at 512^3) against the oracle's
+    adjoint step at every inner point: lam_n and the accumulated gCi, for the
+    Laplacian form and the flux form (whose fluxes the oracle forms from T_n
+    with its own flux routine)."""
+    n = (424, 420, 416)
+    nx, ny, nz = n
+    assert (nx - 2) * (ny - 2) * (nz - 2) >= 2 ** 26
+    say("adjoint large region", form)
+    rng = np.random.default_rng(23)
+    lp = rng.uniform(-1.0, 1.0, (nz, ny, nx))
+    Tn = rng.uniform(1.0, 2.0, (nz, ny, nx))
+    Ci = rng.uniform(0.5, 1.5, (nz, ny, nx))
+    g0 = rng.uniform(-1.0, 1.0, (nz, ny, nx))
+    for a in (lp, Tn, Ci):
+        oracle.halo(a)
+    dx, dy, dz = 1 / (nx - 1), 1 / (ny - 1), 1 / (nz - 1)
+    dt = oracle.time_step(dx, dy, dz, 1.0, oracle.max_all(Ci))
+    g_ref = g0.copy()
+    if form == "laplacian":
+        ln_ref = oracle.adjoint_step(lp, Tn, Ci, g_ref, 1.0, dt, dx, dy, dz)
+    else:
+        q = oracle.flux(Tn, 1.0, dx, dy, dz)
+        ln_ref = oracle.flux_adjoint_step(lp, Ci, q, g_ref, 1.0, dt, dx, dy, dz)
+        del q
+    with grid(n):
+        lpd, Tnd, Cid, gd = dev(lp), dev(Tn), dev(Ci), dev(g0)
+        lnd = torch.zeros_like(lpd)
+        if form == "laplacian":
+            igg.diffusion_step_adjoint(lnd, lpd, Tnd, Cid, gd, 1.0, dt, dx, dy, dz, split=None)
+        else:
+            igg.diffusion_flux_step_adjoint(lnd, lpd, Tnd, Cid, gd, 1.0, dt, dx, dy, dz, split=None)
+        ln, g = host(lnd), host(gd)
+    assert rel_max_err(ln, ln_ref) <= 1e-12
+    assert rel_max_err(g, g_ref) <= 1e-12
