@@ -785,8 +785,8 @@ static bool vec_ok(const StepArgs &a)
 }
 
 // Inner region.  FP64: 128-point (1 KB) tile rows, 16-byte loads, four
-// rows per thread, 16 rows per tile (two rows per thread below 2^26
-// points).  FP32: 256-point (1 KB) rows, 16-byte loads, two rows per
+// rows per thread, 32 rows per tile (512 threads; two rows per thread, 16
+// rows, below 2^26 points).  FP32: 256-point (1 KB) rows, 16-byte loads, two rows per
 // thread, 32 rows over 1024 threads from 2^26 points (16 rows below).
 // FP16: 256-point (512-byte) rows, 8-byte loads, two rows per thread, 8
 // rows (256 threads: 1-3% faster than 512-thread tiles of 16 rows at 256^3
@@ -829,14 +829,16 @@ int launch_step_inner(int dtype, const StepArgs &a, const Box &b, hipStream_t s,
     }
     if (dtype == IGG_F64) {
         if (vec_ok<double, 2>(a)) {
-            // the same 128 x 16 tile over 512 threads of 2 rows (108 registers,
-            // 4 waves per SIMD): 2-3% faster at 256^3 and 384^3, 5% slower at
-            // 512^3, so regions below 2^26 points take it
+            // a 128 x 16 tile over 512 threads of 2 rows (108 registers, 4
+            // waves per SIMD): 2-3% faster at 256^3 and 384^3 than 4 rows per
+            // thread, 5% slower at 512^3, so regions below 2^26 points take it
             static const char *kMidEnv = "IGG_FP64_MIDTILE_MAX_POINTS";
             const char *e = getenv(kMidEnv);
             const int64_t mid_max = (e && *e) ? atoll(e) : ((int64_t)1 << 26);
             if (box_count(b) < mid_max) return run_inner<double, 2, 64, 8, 2>(a, b, s, kInner, yz, nyz, pk);
-            return run_inner<double, 2, 64, 4, 4>(a, b, s, kInner, yz, nyz, pk);
+            // 32-row tiles over 512 threads of 4 rows: fewer y-halo rows per
+            // point than 16-row tiles of 256 threads (512^3: 0.8% faster)
+            return run_inner<double, 2, 64, 8, 4>(a, b, s, kInner, yz, nyz, pk);
         }
         return run_inner<double, 1, 64, 8, 2>(a, b, s, kInner, yz, nyz, pk);
     }
