@@ -43,7 +43,8 @@
  *     N rounds of about 3.4 us put into one stream of the split schedule,
  *     for tests that the streams are ordered by events, not by timing).
  *     Read at each launch (tuning): IGG_FP64_MIDTILE_MAX_POINTS (regions
- *     below it take the 512-thread FP64 step tile), IGG_ZCHUNK, IGG_XCD_REMAP,
+ *     below it take the FP64 step tile of 2 rows per thread and 16 rows,
+ *     larger ones 4 rows per thread and 32 rows), IGG_ZCHUNK, IGG_XCD_REMAP,
  *     IGG_XCD_BLOCK, IGG_XSLAB_ZCHUNK, IGG_XSLAB_REMAP, IGG_SLAB_MARCH,
  *     IGG_ADJ_ZCHUNK, IGG_ADJ_REMAP, IGG_ADJ_XCD_BLOCK, IGG_ADJ_WAVES,
  *     IGG_FLUX_ZCHUNK, IGG_FLUX_REMAP.
