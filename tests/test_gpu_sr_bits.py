@@ -97,3 +97,62 @@ def test_fp16_stochastic_rounding_bits_match_their_definition(split, zmin):
     # and the rounding did something: both directions occur
     rn = x.astype(np.float16).view(np.uint16)
     assert np.any(got != rn)
+
+
+def round_rule_all(x32, w):
+    """FP16 bits of float32 values rounded with words w in every range: the
+    normal range as above; below it (FP16 subnormals, spacing 2^-24) up with
+    probability frac(|x| * 2^24), compared with the top 16 bits of w as a
+    uniform in [0, 1); at or above 65504 to nearest."""
+    ax = np.abs(x32)
+    out = np.empty(x32.shape, np.uint16)
+    normal = (ax >= np.float32(2.0 ** -14)) & (ax < np.float32(65504.0))
+    sub = ax < np.float32(2.0 ** -14)
+    big = ~normal & ~sub
+    out[normal] = round_rule(np.ascontiguousarray(x32[normal]), w[normal])
+    s = ax[sub] * np.float32(2.0 ** 24)
+    f = np.floor(s)
+    u = (w[sub] >> np.uint64(16)).astype(np.float32) * np.float32(2.0 ** -16)
+    m = np.where(u < s - f, f + np.float32(1.0), f).astype(np.float32)
+    out[sub] = np.copysign(m * np.float32(2.0 ** -24), x32[sub]).astype(np.float16).view(np.uint16)
+    with np.errstate(over="ignore"):  # beyond 65520 the nearest FP16 value is infinity
+        out[big] = x32[big].astype(np.float16).view(np.uint16)
+    return out
+
+
+def test_fp16_stochastic_rounding_bits_from_subnormals_to_the_top_binade():
+    """The same check where the step's values fall in the subnormal range
+    as well as the normal range: planes of FP16 subnormals, of ordinary
+    values and of values just below the largest FP16 value, 65504 (a stable
+    step is a convex combination of neighbours, so its results stay at or
+    below 65504 and the range beyond it is not reached)."""
+    n = (70, 40, 36)
+    nx, ny, nz = n
+    seed, counter = 977, 3
+    say("sr bits, every range")
+    rng = np.random.default_rng(9)
+    T0 = np.empty((nz, ny, nx))
+    T0[:12] = rng.uniform(1e-7, 5e-5, (12, ny, nx))
+    T0[12:24] = rng.uniform(1.5, 2.5, (12, ny, nx))
+    T0[24:] = rng.uniform(65000.0, 65504.0, (nz - 24, ny, nx))
+    Ci = rng.uniform(0.25, 0.75, (nz, ny, nx))
+    dx = 1.0 / (nx - 1)
+    dt = dx * dx / 0.75 / 6.1
+    with grid(n, zmarch_min=0):
+        T16, C16 = dev(T0, torch.float16), dev(Ci, torch.float16)
+        exact = torch.empty(T16.shape, dtype=torch.float32, device="cuda")
+        igg.diffusion_step(exact, T16.float().contiguous(), C16.float().contiguous(), 1.0, dt, dx, dx, dx,
+                           split=(16, 2, 2))
+        out = torch.empty_like(T16)
+        igg.diffusion_step(out, T16, C16, 1.0, dt, dx, dx, dx, split=(16, 2, 2),
+                           rnd=igg.rounding("stochastic", seed, counter))
+        torch.cuda.synchronize()
+        x = exact.cpu().numpy()[1:-1, 1:-1, 1:-1]
+        got = out.cpu().numpy().view(np.uint16)[1:-1, 1:-1, 1:-1]
+    ax = np.abs(x)
+    # subnormal results, ordinary ones and ones in the top FP16 binade occur
+    assert np.any(ax < 2.0 ** -14) and np.any((ax >= 1.0) & (ax < 4.0)) and np.any(ax >= 32768.0)
+    w = point_words(n, seed, counter)[1:-1, 1:-1, 1:-1]
+    want = round_rule_all(np.ascontiguousarray(x), w)
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, f"{len(bad)} points differ, first (k, j, i) {tuple(bad[0])}"
