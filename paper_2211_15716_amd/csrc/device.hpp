@@ -70,12 +70,16 @@ __device__ __forceinline__ C flux_div(C qxl, C qxu, C qyl, C qyu, C qzl, C qzu, 
 // PCG hash of Jarzynski and Olano, "Hash Functions for GPU Rendering",
 // JCGT 9(3), 2020: one LCG step of O'Neill's PCG followed by its RXS-M-XS
 // output permutation; a bijection of 32-bit words.
-__host__ __device__ __forceinline__ uint32_t pcg_hash(uint32_t v)
+// pcg_hash(v) = pcg_permute(v * kPcgMul + kPcgInc).
+constexpr uint32_t kPcgMul = 747796405u, kPcgInc = 2891336453u;
+
+__host__ __device__ __forceinline__ uint32_t pcg_permute(uint32_t state)
 {
-    uint32_t state = v * 747796405u + 2891336453u;
     uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
     return (word >> 22u) ^ word;
 }
+
+__host__ __device__ __forceinline__ uint32_t pcg_hash(uint32_t v) { return pcg_permute(v * kPcgMul + kPcgInc); }
 
 // Key of one plane k for the key of a (seed, counter) pair.
 __device__ __forceinline__ uint32_t plane_key(uint32_t key, int k) { return pcg_hash(key + (uint32_t)k); }
@@ -106,11 +110,18 @@ __device__ __forceinline__ uint32_t sr_plane_key(uint32_t key, int k, const SrOr
 // modulo the period): the even point takes its high 16 bits, the odd point
 // its low 16 bits, each as the top half of its 32-bit word (FP16 stochastic
 // rounding uses the top 13 bits of the word in the normal range, the top 16
-// for subnormals).  A kernel holding both points of a pair hashes once for
-// the two (sr_point_bits2).
+// for subnormals).  The hashed word is pk + n for the pair's index n in the
+// plane (mod 2^32), so its first multiply splits as n*kPcgMul, fixed for a
+// point through a z-march, plus pk*kPcgMul, one per plane.  A kernel holding
+// both points of a pair hashes once for the two (sr_point_bits2).
+__device__ __forceinline__ uint32_t sr_pair_index(int gi, int gj, const SrOrigin &so)
+{
+    return (uint32_t)(gi >> 1) + (uint32_t)so.gnh * (uint32_t)gj;
+}
+
 __device__ __forceinline__ uint32_t sr_pair_word(uint32_t pk, int gi, int gj, const SrOrigin &so)
 {
-    return pcg_hash(pk ^ ((uint32_t)(gi >> 1) + (uint32_t)so.gnh * (uint32_t)gj));
+    return pcg_hash(pk + sr_pair_index(gi, gj, so));
 }
 
 __device__ __forceinline__ uint32_t sr_half(uint32_t w, int gi) { return (gi & 1) ? (w << 16) : w; }
@@ -169,6 +180,19 @@ __device__ __forceinline__ _Float16 round_sr(float x, uint32_t w)
     float u = (float)(w >> 16) * (1.0f / 65536.0f);
     float m = (u < s - f) ? f + 1.0f : f;
     return (_Float16)__builtin_copysignf(m * 5.9604644775390625e-08f, x);
+}
+
+// Whether all four values lie in the FP16 normal range, where the gfx950
+// instruction rounds them as round_sr does: the smallest magnitude at least
+// 2^-14 and the sum of magnitudes below 65504 (the sum is at least the
+// largest magnitude, and is not below 65504 for an infinity or a NaN).
+__device__ __forceinline__ bool sr_normal4(const float (&v)[4])
+{
+    const float a0 = __builtin_fabsf(v[0]), a1 = __builtin_fabsf(v[1]), a2 = __builtin_fabsf(v[2]),
+                a3 = __builtin_fabsf(v[3]);
+    const float lo = __builtin_fminf(__builtin_fminf(a0, a1), __builtin_fminf(a2, a3));
+    const float sum = (a0 + a1) + (a2 + a3);
+    return lo >= 6.103515625e-05f && sum < 65504.0f;
 }
 
 template <typename S> struct Store {

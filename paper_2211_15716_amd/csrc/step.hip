@@ -357,8 +357,8 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
     int64_t g = blockIdx.x;
     if constexpr (!WRAP) {
         if (g < z.slab_blocks) {
-            slab_body<S, VEC, SR>(T2, T, Ci, z.ss, a, rx, ry, rz, key,
-                                  g * (BX * TY / 64) + (int64_t)(threadIdx.x / 64), threadIdx.x & 63);
+            slab_body<S, VEC, (SR > 0)>(T2, T, Ci, z.ss, a, rx, ry, rz, key,
+                                        g * (BX * TY / 64) + (int64_t)(threadIdx.x / 64), threadIdx.x & 63);
             return;
         }
     }
@@ -445,6 +445,90 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
         hx[r] = own_h ? T[(int64_t)kb * sxy + col[r] - i + xh] : S(0);
     }
     V yh = hy ? ldv(T, kb, colhy) : V{};
+    // SR == 2 (rows of 4-point vectors whose global x origin and x period
+    // are even, so every vector holds two whole hash pairs): the hash input
+    // multiple of each row's first pair, fixed for the march, and the step
+    // from a vector's first pair to its second
+    uint32_t hmul[RY], hstep = 0;
+    if constexpr (SR == 2) {
+        static_assert(VEC == 4 && !WRAP, "whole pairs need 4-point vectors");
+        const int g0 = sr_wrap(i + z.so.ox, z.so.px), g2 = sr_wrap(i + 2 + z.so.ox, z.so.px);
+        hstep = (uint32_t)((g2 >> 1) - (g0 >> 1)) * kPcgMul;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) hmul[r] = sr_pair_index(g0, sr_wrap(jr[r] + z.so.oy, z.so.py), z.so) * kPcgMul;
+    }
+
+    // SR == 2, one plane: every row computed and rounded before the stores
+    // (a row past the box computes values it does not store), each vector
+    // with the instruction, and all RY vectors redone in round_sr when one
+    // of their values lies outside the FP16 normal range: one test and no
+    // branch per value in the common case
+    auto sr2_rows = [&](int k, int buf, uint32_t pk) {
+      if constexpr (SR == 2) {
+        typedef _Float16 H2 __attribute__((ext_vector_type(2)));
+        const uint32_t pmul = pk * kPcgMul + kPcgInc;
+        C v[RY][VEC];
+        uint32_t w[RY][VEC];
+        V out[RY];
+        bool normal = true;
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            const int lr = 1 + ty * RY + r;
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) {
+                const int lc = 1 + tx * VEC + q;
+                const C c = widen<C>(lane_elem<S, VEC>(tc[r], q));
+                const C xm = (q == 0) ? tile[buf][lr][lc - 1] : widen<C>(lane_elem<S, VEC>(tc[r], q - 1));
+                const C xp = (q == VEC - 1) ? tile[buf][lr][lc + 1] : widen<C>(lane_elem<S, VEC>(tc[r], q + 1));
+                const C ym = (r == 0) ? tile[buf][lr - 1][lc] : widen<C>(lane_elem<S, VEC>(tc[r - 1], q));
+                const C yp = (r == RY - 1) ? tile[buf][lr + 1][lc] : widen<C>(lane_elem<S, VEC>(tc[r + 1], q));
+                v[r][q] = diffuse<C>(c, xm, xp, ym, yp, widen<C>(lane_elem<S, VEC>(tm[r], q)),
+                                     widen<C>(lane_elem<S, VEC>(tp[r], q)), widen<C>(lane_elem<S, VEC>(ci[r], q)), a,
+                                     rx, ry, rz);
+            }
+            const uint32_t s0 = hmul[r] + pmul;
+            w[r][0] = pcg_permute(s0);
+            w[r][1] = w[r][0] << 16;
+            w[r][2] = pcg_permute(s0 + hstep);
+            w[r][3] = w[r][2] << 16;
+            H2 h0 = __builtin_bit_cast(H2, w[r][0]), h1 = __builtin_bit_cast(H2, w[r][2]);
+            h0 = __builtin_amdgcn_cvt_sr_f16_f32(h0, v[r][0], w[r][0], false);
+            h0 = __builtin_amdgcn_cvt_sr_f16_f32(h0, v[r][1], w[r][1], true);
+            h1 = __builtin_amdgcn_cvt_sr_f16_f32(h1, v[r][2], w[r][2], false);
+            h1 = __builtin_amdgcn_cvt_sr_f16_f32(h1, v[r][3], w[r][3], true);
+            out[r] = __builtin_shufflevector(h0, h1, 0, 1, 2, 3);
+            normal = normal && sr_normal4(v[r]);
+        }
+        if (!normal) {
+#pragma unroll
+            for (int r = 0; r < RY; ++r)
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) out[r][q] = round_sr(v[r][q], w[r][q]);
+        }
+#pragma unroll
+        for (int r = 0; r < RY; ++r) {
+            if (!crow[r]) continue;
+            S *dst = T2 + (int64_t)k * sxy + col[r];
+            if (xin && i >= bb.i0 && i + VEC <= bb.i1) {
+                __builtin_nontemporal_store(out[r], reinterpret_cast<V *>(dst));
+            } else if (xin) {
+#pragma unroll
+                for (int q = 0; q < VEC; ++q)
+                    if (i + q >= bb.i0 && i + q < bb.i1) dst[q] = out[r][q];
+            }
+            // the x exchange fused into the store, as below
+            if (z.xh.on_lo && xin && i <= z.xh.lo && i + VEC > z.xh.lo) {
+                const int q = z.xh.lo - i;
+                if (i + q >= bb.i0 && i + q < bb.i1)
+                    dst[q + nx - 1 - z.xh.lo + z.xh.d_lo] = lane_elem_dyn<S, VEC>(out[r], q);
+            }
+            if (z.xh.on_hi && xin && i <= z.xh.hi && i + VEC > z.xh.hi) {
+                const int q = z.xh.hi - i;
+                if (i + q >= bb.i0 && i + q < bb.i1) dst[q - z.xh.hi + z.xh.d_hi] = lane_elem_dyn<S, VEC>(out[r], q);
+            }
+        }
+      }
+    };
 
     for (int k = kb; k < ke; ++k) {
         const int buf = (k - kb) & 1;
@@ -473,6 +557,9 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
         }
         __syncthreads();
         const uint32_t pk = stochastic ? sr_plane_key(key, k, z.so) : 0u;
+        if constexpr (SR == 2) {
+            sr2_rows(k, buf, pk);
+        } else {
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
             if (!crow[r]) continue;
@@ -546,6 +633,7 @@ k_step_zmarch(S *__restrict__ T2, const S *__restrict__ T, const S *__restrict__
                 const int q = z.xh.hi - ix;
                 if (i + q >= c0 && i + q < c1) dst[q - z.xh.hi + z.xh.d_hi] = lane_elem_dyn<S, VEC>(out, q);
             }
+        }
         }
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
@@ -759,8 +847,18 @@ static int run_zmarch(const StepArgs &a, const Box *b, int nbox, hipStream_t s, 
     // a wrapped tile addresses its arrays from w2 points before each row
     const int64_t off = WRAP ? z.w2 : 0;
     bool sr_launched = false;
+    if constexpr (std::is_same<S, _Float16>::value && VEC == 4 && !WRAP) {
+        // every 4-point vector holds two whole hash pairs when the global x
+        // origin and the x period are even (vectors start at multiples of 4)
+        if (a.stochastic && a.so.ox % 2 == 0 && a.so.px % 2 == 0) {
+            hipLaunchKernelGGL((k_step_zmarch<S, VEC, BX, TY, RY, WRAP, 2>), dim3((unsigned)blocks), dim3(BX * TY),
+                               0, s, (S *)a.T2, (const S *)a.T, (const S *)a.Ci, z, (C)a.a, (C)a.rx, (C)a.ry,
+                               (C)a.rz, a.key);
+            sr_launched = true;
+        }
+    }
     if constexpr (std::is_same<S, _Float16>::value) {
-        if (a.stochastic) {
+        if (a.stochastic && !sr_launched) {
             hipLaunchKernelGGL((k_step_zmarch<S, VEC, BX, TY, RY, WRAP, 1>), dim3((unsigned)blocks), dim3(BX * TY),
                                0, s, (S *)a.T2 - off, (const S *)a.T - off, (const S *)a.Ci - off, z, (C)a.a,
                                (C)a.rx, (C)a.ry, (C)a.rz, a.key);
