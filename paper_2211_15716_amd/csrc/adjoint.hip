@@ -51,11 +51,24 @@ __device__ __forceinline__ void adj_cell(C l, C m0, C mxm, C mxp, C mym, C myp, 
     }
 }
 
+// The image rows of row j at plane k under YZImg: (jd, k), (j, kd) and
+// (jd, kd) for the halo row jd and plane kd that take row j and plane k
+// (-1: none).  f(jj, kk) is called for each.
+template <typename F>
+__device__ __forceinline__ void yz_images(const YZImg &yz, int j, int k, F &&f)
+{
+    const int jd = j == yz.jl ? yz.ny - 1 : (j == yz.jh ? 0 : -1);
+    const int kd = k == yz.kl ? yz.nz - 1 : (k == yz.kh ? 0 : -1);
+    if (jd >= 0) f(jd, k);
+    if (kd >= 0) f(j, kd);
+    if (jd >= 0 && kd >= 0) f(jd, kd);
+}
+
 template <typename C, int FORM>
 __global__ void __launch_bounds__(256)
 k_adj_boxes(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restrict__ Tn,
             const C *__restrict__ Ci, C *__restrict__ gCi, BoxSet bs, int nx, int ny, C a, C rx, C ry,
-            C rz, C lamf, XHalo xh)
+            C rz, C lamf, XHalo xh, YZImg yz)
 {
     int i, j, k;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -72,6 +85,14 @@ k_adj_boxes(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restrict
     // x exchange of lam_n fused into the store
     if (xh.on_lo && i == xh.lo) lam_n[p - i + nx - 1 + xh.d_lo] = ln;
     if (xh.on_hi && i == xh.hi) lam_n[p - i + xh.d_hi] = ln;
+    // y/z halo planes whose image is this point, each with its x exchange
+    if (yz.on)
+        yz_images(yz, j, k, [&](int jj, int kk) {
+            const int64_t q0 = sz * kk + sy * jj;
+            lam_n[q0 + i] = ln;
+            if (xh.on_lo && i == xh.lo) lam_n[q0 + nx - 1 + xh.d_lo] = ln;
+            if (xh.on_hi && i == xh.hi) lam_n[q0 + xh.d_hi] = ln;
+        });
 }
 
 struct AdjTile {
@@ -83,6 +104,7 @@ struct AdjTile {
     int remap;
     int rblock;  // mode 2: x-rows of tiles per block dealt to one XCD
     XHalo xh;
+    YZImg yz;
 };
 
 template <typename C, int VEC> struct AVec {
@@ -131,6 +153,7 @@ k_adj_zmarch(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restric
              const C *__restrict__ Ci, C *__restrict__ gCi, AdjTile z, C a, C rx, C ry, C rz, C lamf)
 {
     using V = typename AVec<C, VEC>::type;
+    static_assert(BX == 64, "a wave holds one thread row (the y/z image stores rely on it)");
     constexpr int TW = BX * VEC, TH = TY * RY, LH = TH + 2, LW = TW + 2;
     __shared__ C smu[2][LH][LW];
     __shared__ C sT[2][LH][LW];
@@ -301,6 +324,20 @@ k_adj_zmarch(C *__restrict__ lam_n, const C *__restrict__ lp, const C *__restric
                 lam_n[p - i + nx - 1 + z.xh.d_lo] = el_dyn<C, VEC>(lo, z.xh.lo - i);
             if (z.xh.on_hi && xin && i <= z.xh.hi && i + VEC > z.xh.hi && z.xh.hi >= z.b.i0 && z.xh.hi < z.b.i1)
                 lam_n[p - i + z.xh.d_hi] = el_dyn<C, VEC>(lo, z.xh.hi - i);
+            // y/z halo rows whose image is this row, each with its x exchange
+            // (a wave holds one row, BX being 64: the row index is the same
+            // in every lane, and the branch is taken by whole waves)
+            if (z.yz.on && xin)
+                yz_images(z.yz, __builtin_amdgcn_readfirstlane(jb + ty * RY + r), k, [&](int jj, int kk) {
+                    C *row = lam_n + (int64_t)kk * sxy + (int64_t)jj * nx;
+#pragma unroll
+                    for (int q = 0; q < VEC; ++q)
+                        if (i + q >= z.b.i0 && i + q < z.b.i1) row[i + q] = el<C, VEC>(lo, q);
+                    if (z.xh.on_lo && i <= z.xh.lo && i + VEC > z.xh.lo && z.xh.lo >= z.b.i0 && z.xh.lo < z.b.i1)
+                        row[nx - 1 + z.xh.d_lo] = el_dyn<C, VEC>(lo, z.xh.lo - i);
+                    if (z.xh.on_hi && i <= z.xh.hi && i + VEC > z.xh.hi && z.xh.hi >= z.b.i0 && z.xh.hi < z.b.i1)
+                        row[z.xh.d_hi] = el_dyn<C, VEC>(lo, z.xh.hi - i);
+                });
         }
 #pragma unroll
         for (int r = 0; r < RY; ++r) {
@@ -335,7 +372,7 @@ static int run_boxes(const AdjArgs &a, const Box *b, int nb, hipStream_t s)
     if (threads == 0) return IGG_OK;
     hipLaunchKernelGGL((k_adj_boxes<C, FORM>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
                        (C *)a.lam_n, (const C *)a.lp, (const C *)a.Tn, (const C *)a.Ci, (C *)a.gCi, bs,
-                       a.nx, a.ny, (C)a.a, (C)a.rx, (C)a.ry, (C)a.rz, (C)a.lamf, a.xh);
+                       a.nx, a.ny, (C)a.a, (C)a.rx, (C)a.ry, (C)a.rz, (C)a.lamf, a.xh, a.yz);
     IGG_HIP(hipGetLastError());
     return IGG_OK;
 }
@@ -369,6 +406,7 @@ static int run_zmarch(const AdjArgs &a, const Box &b, hipStream_t s)
     // 24); at 512^3 blocks of 16 are 4% faster
     z.rblock = std::max(1, env_int("IGG_ADJ_XCD_BLOCK", 4));
     z.xh = a.xh;
+    z.yz = a.yz;
     int64_t blocks = (int64_t)z.ntx * z.nty * ((depth + zc - 1) / zc);
     if (blocks == 0) return IGG_OK;
     hipLaunchKernelGGL((k_adj_zmarch<C, VEC, BX, TY, RY, FORM, WAVES>), dim3((unsigned)blocks), dim3(BX * TY), 0, s,

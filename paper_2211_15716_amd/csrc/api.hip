@@ -600,14 +600,18 @@ static int adjoint_step(int form, const igg_field *lam_n, const igg_field *lam_n
     Box all{1, g.n[0] - 1, 1, g.n[1] - 1, 1, g.n[2] - 1};
     if (split && self_halo_ok() && (g.schedule < 0 || g.schedule == 3)) {
         // one rank, periodic in every dimension: one launch over every inner
-        // point (storing the x halo of lam_n), then one launch that fills the
-        // y and z halo planes from their images; the adjoint runs its chain
-        // serially anyway, so the boundary has nothing to overlap
+        // point, which also stores the x halo of lam_n and, for every inner
+        // point that is the image of y/z halo points, those points (the
+        // adjoint runs its chain serially anyway, so the boundary has nothing
+        // to overlap)
+        AdjArgs a0 = args[0];
+        const bool sized = lam_n[0].size[1] == g.n[1] && lam_n[0].size[2] == g.n[2];
+        if (sized) a0.yz = YZImg{1, g.ol[1] - 1, g.n[1] - g.ol[1], g.ol[2] - 1, g.n[2] - g.ol[2], g.n[1], g.n[2]};
         if ((rc = timing_mark(s, 0))) return rc;
-        if ((rc = launch_adjoint_inner(dt_, args[0], all, s))) return rc;
+        if ((rc = launch_adjoint_inner(dt_, a0, all, s))) return rc;
         if ((rc = timing_mark(s, 0))) return rc;
         if (g.timing) { g.t_launches++; g.t_points += box_points(all); }
-        return launch_halo_self_yz(lam_n[0], s);
+        return sized ? IGG_OK : launch_halo_self_yz(lam_n[0], s);
     }
     if (!split) {
         for (int r = 0; r < P; ++r) {

@@ -183,6 +183,18 @@ int launch_halo_self_yz(const igg_field &f, hipStream_t s);
 // Send buffer of rank r, slot f (a field index of the halo update), side.
 unsigned char *halo_send_plane(int r, int f, int side);
 
+// The y and z halo planes of lam_n filled by the adjoint kernels' stores,
+// on one rank that is its own neighbour in every dimension: halo row ny-1
+// is the image of row jl = ol-1, row 0 that of row jh = ny-ol (z likewise,
+// kl and kh), and a point's image has the same x index (its x-halo copies
+// come with the x exchange).  Each point of the four planes has one image
+// among the inner points, so these stores fill the planes.
+struct YZImg {
+    int on;
+    int jl, jh, kl, kh;
+    int ny, nz;
+};
+
 struct AdjArgs {
     void *lam_n;
     const void *lp;
@@ -194,6 +206,7 @@ struct AdjArgs {
     XHalo xh;              // x exchange of lam_n fused into the stores
     int form = 0;          // 0: Laplacian step, 1: staggered flux form
     double lamf = 0.0;     // lam, for the flux form's face fluxes
+    YZImg yz{};            // y/z halo of lam_n stored with its images (on: set)
 };
 int launch_adjoint_boxes(int dtype, const AdjArgs &a, const Box *b, int nb, hipStream_t s);
 int launch_adjoint_inner(int dtype, const AdjArgs &a, const Box &b, hipStream_t s);
