@@ -143,6 +143,34 @@ def test_checkpointed_gradient_non_periodic_matches_oracle(periods):
                 assert np.max(np.abs(inner(gC) - inner(gC_ref))) <= 1e-12 * np.max(np.abs(inner(gC_ref))), sched
 
 
+@pytest.mark.parametrize("ol", [(3, 3, 3), (2, 3, 4)])
+@pytest.mark.parametrize("zmin", [0, None])
+def test_checkpointed_gradient_wider_overlaps_matches_oracle(ol, zmin):
+    """Periodic grid with overlaps above 2: on one rank the boundary-first
+    adjoint fills the y/z halo of lambda from the images of its halo points
+    (rows and planes ol-1 and n-ol) as it stores them, in the z-march
+    (zmin 0) and the small-grid kernels (zmin None); every schedule gives
+    the oracle's loss and gradients."""
+    say("wider-overlap gradient", ol, zmin)
+    n = (40, 34, 30)
+    nt = 9
+    T0, Ci, Tobs = synth.uniform_fields(*n, seed=67, lo=0.3, hi=0.9, n=3)
+    for a in (T0, Ci, Tobs):
+        oracle.halo(a, ol, (1, 1, 1))
+    dx = 1 / 39
+    dt = oracle.time_step(dx, dx, dx, 1.0, oracle.max_all(Ci))
+    L_ref, gT_ref, gC_ref = oracle.gradient(T0, Ci, Tobs, nt, 1.0, dt, dx, dx, dx, ol=ol)
+    with grid(n, overlaps=ol, zmarch_min=zmin):
+        for split in (None, (16, 4, 4)):
+            prob = diffusion.Problem(1.0, dt, dx, dx, dx, split=split)
+            for sched in [("store_all",), ("periodic", 4)]:
+                L, gT, gC, _ = diffusion.loss_and_grad(dev(T0), dev(Ci), dev(Tobs), prob, nt, sched)
+                gT, gC = host(gT), host(gC)
+                assert abs(L - L_ref) <= 1e-12 * L_ref
+                assert np.max(np.abs(inner(gT) - inner(gT_ref))) <= 1e-12 * np.max(np.abs(inner(gT_ref))), sched
+                assert np.max(np.abs(inner(gC) - inner(gC_ref))) <= 1e-12 * np.max(np.abs(inner(gC_ref))), sched
+
+
 def test_autograd_function_matches_sweep():
     say("autograd")
     n = (36, 30, 28)
