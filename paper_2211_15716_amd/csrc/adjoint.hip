@@ -51,17 +51,21 @@ __device__ __forceinline__ void adj_cell(C l, C m0, C mxm, C mxp, C mym, C myp, 
     }
 }
 
-// The image rows of row j at plane k under YZImg: (jd, k), (j, kd) and
-// (jd, kd) for the halo row jd and plane kd that take row j and plane k
-// (-1: none).  f(jj, kk) is called for each.
+// The y/z halo rows of row j at plane k under YZImg: every (jj, kk) other
+// than (j, k) with jj in {j, ny-1 if j = jl, 0 if j = jh} and kk in {k,
+// nz-1 if k = kl, 0 if k = kh} (with n = ol+1 one row is the image of both
+// halo rows).  f(jj, kk) is called for each.
 template <typename F>
 __device__ __forceinline__ void yz_images(const YZImg &yz, int j, int k, F &&f)
 {
-    const int jd = j == yz.jl ? yz.ny - 1 : (j == yz.jh ? 0 : -1);
-    const int kd = k == yz.kl ? yz.nz - 1 : (k == yz.kh ? 0 : -1);
-    if (jd >= 0) f(jd, k);
-    if (kd >= 0) f(j, kd);
-    if (jd >= 0 && kd >= 0) f(jd, kd);
+    if (j != yz.jl && j != yz.jh && k != yz.kl && k != yz.kh) return;
+    const int js[3] = {j, j == yz.jl ? yz.ny - 1 : -1, j == yz.jh ? 0 : -1};
+    const int ks[3] = {k, k == yz.kl ? yz.nz - 1 : -1, k == yz.kh ? 0 : -1};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+            if ((a | b) && js[a] >= 0 && ks[b] >= 0) f(js[a], ks[b]);
 }
 
 template <typename C, int FORM>

@@ -53,6 +53,47 @@ def test_random_grids_match_oracle(case, zmin):
             assert np.array_equal(a, b), name
 
 
+def _adjoint_cases(count, seed):
+    """Every other case periodic in all dimensions (one rank: the adjoint
+    kernel stores the y/z halo of lambda from their images)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(count):
+        ol = tuple(int(v) for v in rng.integers(2, 5, size=3))
+        n = tuple(int(rng.integers(o + 1, o + 1 + int(rng.choice([2, 9, 40, 90])))) for o in ol)
+        periods = (1, 1, 1) if q % 2 == 0 else tuple(int(v) for v in rng.integers(0, 2, size=3))
+        split = None if rng.random() < 0.25 else tuple(int(rng.integers(o, o + 20)) for o in ol)
+        out.append((n, ol, periods, split))
+    return out
+
+
+@pytest.mark.parametrize("case", _adjoint_cases(16, 77))
+@pytest.mark.parametrize("zmin", [0, None])
+def test_random_grids_adjoint_step_matches_oracle(case, zmin):
+    """One FP64 adjoint step against the oracle's adjoint step and halo
+    update: lambda_n at every point (halos included: periodic images, zero
+    in non-periodic dimensions) and the Ci gradient on the inner points."""
+    n, ol, periods, split = case
+    nx, ny, nz = n
+    lp, Tn, Ci, g0 = synth.uniform_fields(nx, ny, nz, seed=sum(n) + 1, lo=0.2, hi=1.0, n=4)
+    for a in (lp, Tn, Ci):
+        oracle.halo(a, ol, periods)
+    d = tuple(1.0 / (m - 1) for m in n)
+    dt = oracle.time_step(*d, 1.0, oracle.max_all(Ci))
+    g_ref = g0.copy()
+    ref = oracle.adjoint_step(lp, Tn, Ci, g_ref, 1.0, dt, *d)
+    oracle.halo(ref, ol, periods)
+    with grid(n, periods, ol, zmarch_min=zmin):
+        say("random grid adjoint", n, ol, periods, split, zmin)
+        ln = torch.zeros(lp.shape, dtype=torch.float64, device="cuda")
+        gC = dev(g0)
+        igg.diffusion_step_adjoint(ln, dev(lp), dev(Tn), dev(Ci), gC, 1.0, dt, *d, split=split)
+        got, g = host(ln), host(gC)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    i3 = (slice(1, -1),) * 3
+    assert np.max(np.abs(g[i3] - g_ref[i3])) <= 1e-12 * np.max(np.abs(g_ref[i3]))
+
+
 @pytest.mark.parametrize("n,split", [((4096, 4096, 6), (16, 2, 2)), ((6, 6, 1 << 22), None)])
 def test_extreme_aspect_ratios(n, split):
     """Grids of 10^8 points in a long thin shape (a 16.8 M-point plane, a
