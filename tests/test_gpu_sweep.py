@@ -69,11 +69,16 @@ def _adjoint_cases(count, seed):
 
 @pytest.mark.parametrize("case", _adjoint_cases(16, 77))
 @pytest.mark.parametrize("zmin", [0, None])
-def test_random_grids_adjoint_step_matches_oracle(case, zmin):
-    """One FP64 adjoint step against the oracle's adjoint step and halo
-    update: lambda_n at every point (halos included: periodic images, zero
-    in non-periodic dimensions) and the Ci gradient on the inner points."""
+@pytest.mark.parametrize("form", ["laplacian", "flux"])
+def test_random_grids_adjoint_step_matches_oracle(case, zmin, form):
+    """One FP64 adjoint step, Laplacian and staggered flux form, against the
+    oracle's adjoint step and halo update: lambda_n at every point (halos
+    included: periodic images, zero in non-periodic dimensions) and the Ci
+    gradient on the inner points.  The flux form's split widths are at least
+    ol+1."""
     n, ol, periods, split = case
+    if form == "flux" and split is not None:
+        split = tuple(max(w, o + 1) for w, o in zip(split, ol))
     nx, ny, nz = n
     lp, Tn, Ci, g0 = synth.uniform_fields(nx, ny, nz, seed=sum(n) + 1, lo=0.2, hi=1.0, n=4)
     for a in (lp, Tn, Ci):
@@ -81,13 +86,17 @@ def test_random_grids_adjoint_step_matches_oracle(case, zmin):
     d = tuple(1.0 / (m - 1) for m in n)
     dt = oracle.time_step(*d, 1.0, oracle.max_all(Ci))
     g_ref = g0.copy()
-    ref = oracle.adjoint_step(lp, Tn, Ci, g_ref, 1.0, dt, *d)
+    if form == "flux":
+        ref = oracle.flux_adjoint_step(lp, Ci, oracle.flux(Tn, 1.0, *d), g_ref, 1.0, dt, *d)
+    else:
+        ref = oracle.adjoint_step(lp, Tn, Ci, g_ref, 1.0, dt, *d)
     oracle.halo(ref, ol, periods)
     with grid(n, periods, ol, zmarch_min=zmin):
-        say("random grid adjoint", n, ol, periods, split, zmin)
+        say("random grid adjoint", form, n, ol, periods, split, zmin)
         ln = torch.zeros(lp.shape, dtype=torch.float64, device="cuda")
         gC = dev(g0)
-        igg.diffusion_step_adjoint(ln, dev(lp), dev(Tn), dev(Ci), gC, 1.0, dt, *d, split=split)
+        step = igg.diffusion_flux_step_adjoint if form == "flux" else igg.diffusion_step_adjoint
+        step(ln, dev(lp), dev(Tn), dev(Ci), gC, 1.0, dt, *d, split=split)
         got, g = host(ln), host(gC)
     assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
     i3 = (slice(1, -1),) * 3
