@@ -70,17 +70,21 @@ def _adjoint_cases(count, seed):
 @pytest.mark.parametrize("case", _adjoint_cases(16, 77))
 @pytest.mark.parametrize("zmin", [0, None])
 @pytest.mark.parametrize("form", ["laplacian", "flux"])
-def test_random_grids_adjoint_step_matches_oracle(case, zmin, form):
-    """One FP64 adjoint step, Laplacian and staggered flux form, against the
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_random_grids_adjoint_step_matches_oracle(case, zmin, form, dtype):
+    """One adjoint step, Laplacian and staggered flux form, against the
     oracle's adjoint step and halo update: lambda_n at every point (halos
     included: periodic images, zero in non-periodic dimensions) and the Ci
-    gradient on the inner points.  The flux form's split widths are at least
-    ol+1."""
+    gradient on the inner points; FP64 within 1e-12, FP32 (inputs rounded to
+    FP32 for both sides) within 1e-5.  The flux form's split widths are at
+    least ol+1."""
     n, ol, periods, split = case
     if form == "flux" and split is not None:
         split = tuple(max(w, o + 1) for w, o in zip(split, ol))
     nx, ny, nz = n
     lp, Tn, Ci, g0 = synth.uniform_fields(nx, ny, nz, seed=sum(n) + 1, lo=0.2, hi=1.0, n=4)
+    if dtype == "f32":
+        lp, Tn, Ci, g0 = (a.astype(np.float32).astype(np.float64) for a in (lp, Tn, Ci, g0))
     for a in (lp, Tn, Ci):
         oracle.halo(a, ol, periods)
     d = tuple(1.0 / (m - 1) for m in n)
@@ -92,15 +96,17 @@ def test_random_grids_adjoint_step_matches_oracle(case, zmin, form):
         ref = oracle.adjoint_step(lp, Tn, Ci, g_ref, 1.0, dt, *d)
     oracle.halo(ref, ol, periods)
     with grid(n, periods, ol, zmarch_min=zmin):
-        say("random grid adjoint", form, n, ol, periods, split, zmin)
-        ln = torch.zeros(lp.shape, dtype=torch.float64, device="cuda")
-        gC = dev(g0)
+        say("random grid adjoint", form, dtype, n, ol, periods, split, zmin)
+        t = DT[dtype]
+        ln = torch.zeros(lp.shape, dtype=t, device="cuda")
+        gC = dev(g0, t)
         step = igg.diffusion_flux_step_adjoint if form == "flux" else igg.diffusion_step_adjoint
-        step(ln, dev(lp), dev(Tn), dev(Ci), gC, 1.0, dt, *d, split=split)
-        got, g = host(ln), host(gC)
-    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+        step(ln, dev(lp, t), dev(Tn, t), dev(Ci, t), gC, 1.0, dt, *d, split=split)
+        got, g = host(ln).astype(np.float64), host(gC).astype(np.float64)
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    assert np.max(np.abs(got - ref)) <= tol * np.max(np.abs(ref))
     i3 = (slice(1, -1),) * 3
-    assert np.max(np.abs(g[i3] - g_ref[i3])) <= 1e-12 * np.max(np.abs(g_ref[i3]))
+    assert np.max(np.abs(g[i3] - g_ref[i3])) <= tol * np.max(np.abs(g_ref[i3]))
 
 
 @pytest.mark.parametrize("n,split", [((4096, 4096, 6), (16, 2, 2)), ((6, 6, 1 << 22), None)])
