@@ -109,6 +109,37 @@ def test_random_grids_adjoint_step_matches_oracle(case, zmin, form, dtype):
     assert np.max(np.abs(g[i3] - g_ref[i3])) <= tol * np.max(np.abs(g_ref[i3]))
 
 
+@pytest.mark.parametrize("case", _adjoint_cases(16, 91))
+@pytest.mark.parametrize("zmin", [0, None])
+def test_random_grids_flux_form_matches_oracle(case, zmin):
+    """Three FP64 steps of the staggered flux form against the oracle: the
+    cell field and the three face fields at every point (halos included);
+    split widths at least ol+1."""
+    n, ol, periods, split = case
+    if split is not None:
+        split = tuple(max(w, o + 1) for w, o in zip(split, ol))
+    nx, ny, nz = n
+    T0, Ci = synth.noisy_state_uniform_ci(nx, ny, nz, seed=sum(n) + 2, noise=1e-2)
+    oracle.halo(T0, ol, periods)
+    oracle.halo(Ci, ol, periods)
+    d = tuple(1.0 / (m - 1) for m in n)
+    dt = oracle.time_step(*d, 1.0, oracle.max_all(Ci))
+    nt = 3
+    ref, qref = oracle.flux_run(T0, Ci, nt, 1.0, dt, *d, overlaps=ol, periods=periods, return_q=True)
+    with grid(n, periods, ol, zmarch_min=zmin):
+        say("random grid flux", n, ol, periods, split, zmin)
+        T, C = dev(T0), dev(Ci)
+        T2 = T.clone()
+        q = [torch.zeros(sh, dtype=torch.float64, device="cuda") for sh in oracle.face_shapes(T0)]
+        for _ in range(nt):
+            igg.diffusion_flux_step(T2, T, C, *q, 1.0, dt, *d, split=split)
+            T, T2 = T2, T
+        got = [host(T)] + [host(x) for x in q]
+    assert np.max(np.abs(got[0] - ref)) <= 1e-12 * np.max(np.abs(ref))
+    for a, b in zip(got[1:], qref):
+        assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
+
+
 @pytest.mark.parametrize("n,split", [((4096, 4096, 6), (16, 2, 2)), ((6, 6, 1 << 22), None)])
 def test_extreme_aspect_ratios(n, split):
     """Grids of 10^8 points in a long thin shape (a 16.8 M-point plane, a
