@@ -84,7 +84,12 @@ def _global_problem(N, periods, ol, seed):
     return T0, Ci
 
 
-@pytest.mark.parametrize("n,dims,periods,ol", CASES + [((70, 40, 36), (2, 2, 2), (1, 1, 1), (2, 2, 2))])
+# rows of 72 points take the kernels of 4-point vectors: with x overlap 3 the
+# second x rank's origin is odd (69), so its FP16 stochastic rounding takes
+# the per-pair hash while the first rank's takes whole pairs per vector
+@pytest.mark.parametrize("n,dims,periods,ol", CASES + [((70, 40, 36), (2, 2, 2), (1, 1, 1), (2, 2, 2)),
+                                                      ((72, 40, 36), (2, 1, 1), (1, 1, 1), (3, 2, 2)),
+                                                      ((72, 40, 36), (2, 2, 1), (1, 1, 1), (2, 2, 2))])
 @pytest.mark.parametrize("dt_name", ["f64", "f32", "f16"])
 def test_step_ranks_equal_global_block(n, dims, periods, ol, dt_name):
     """nt steps on the ranks (split and unsplit) give the global block's
