@@ -279,7 +279,10 @@ int diffusion_dt(const igg_field *Ci, double lam, double dx, double dy, double d
  * FP64 or FP32 (IGG_ERR_DTYPE for FP16).  `split` as in diffusion_step,
  * except that by default the slabs, the update and the inner region run as
  * one chain on `stream` at every size (the adjoint kernel is partly
- * latency-bound and runs slower with the slabs beside it).
+ * latency-bound and runs slower with the slabs beside it); on one rank that
+ * is periodic in every dimension, one launch computes every inner point and
+ * stores lam_n's halo with it (the x exchange, and each y/z halo point from
+ * the inner point that is its image).
  * Errors: as diffusion_step; IGG_ERR_ALIAS if lam_n or gCi overlaps an input
  * or each other. */
 int diffusion_step_adjoint(const igg_field *lam_n, const igg_field *lam_np1,
