@@ -3,10 +3,13 @@
 // kernels are measured against beside the 8 TB/s peak.
 //
 // dst[w][i] = sum_r src[r][i], FP64, every array read or written exactly
-// once.  Each thread moves four independent 16-byte vectors per array per
-// iteration with non-temporal loads and stores (the accesses the stencil
-// kernels use for the arrays they touch once), so many loads are in flight
-// per wave.
+// once, with non-temporal loads and stores (the accesses the stencil
+// kernels use for the arrays they touch once).  Each thread moves one
+// 16-byte vector per array, in work-groups of 256 threads over the whole
+// array: on MI355X this streams faster than four vectors per thread (2R1W
+// 6.40-6.46 against 6.24-6.32 TB/s), two (6.24), 512- or 1024-thread
+// work-groups (5.83, 5.37 with four) or a grid-stride loop over fewer
+// work-groups (5.82-5.98), so it is the ceiling the kernels are held to.
 #include "host.hpp"
 
 namespace igg {
@@ -19,7 +22,7 @@ struct ProbeArgs {
     int64_t n2;  // 16-byte vectors per array
 };
 
-constexpr int kProbeThreads = 256, kProbeUnroll = 4;
+constexpr int kProbeThreads = 256, kProbeUnroll = 1;
 
 template <int NS, int ND>
 __global__ void __launch_bounds__(kProbeThreads) k_stream_probe(ProbeArgs p)
