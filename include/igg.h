@@ -429,8 +429,8 @@ int igg_timing_read(double *ms, int64_t *launches, int64_t *points, double *boun
  * read/write mix reaches on the current device, the achievable ceiling the
  * stencil kernels are compared with beside the vendor peak.  For i < n:
  * dst[w][i] = src[0][i] + ... + src[nsrc-1][i] (FP64) for every w, each
- * array read or written once, with 16-byte non-temporal accesses and four
- * independent vectors per thread.
+ * array read or written once, with 16-byte non-temporal accesses, one
+ * vector per array and thread in work-groups of 256 threads.
  *   src, dst   host arrays of nsrc (1..4) and ndst (1..4) device pointers to
  *              n doubles each, 16-byte aligned; the caller owns them.
  *   n          doubles per array, even.
